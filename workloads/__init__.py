@@ -1,0 +1,217 @@
+"""Seeded synthetic problem descriptions for the staggered-grid P_N solver.
+
+This module only describes *inputs*: domain, grid size, moment order, boundary
+type, CFL number, final time, and the material / source / initial-condition
+fields as vectorised functions f(t, x, y) of physical coordinates.  It holds
+none of the scheme's arithmetic (no moment matrices, no staggered grids, no
+time step rule); the oracle and the GPU library each sample these functions on
+their own grids.
+
+The problems follow the paper's workloads (Sect. 6):
+  * line source   (Sect. 6.4): isotropic Gaussian of the zeroth moment in a
+    purely scattering medium, sigma_s0 = 1;
+  * checkerboard  (Sect. 6.3): [0,7]^2 lattice with unit absorbing blocks,
+    isotropic unit source in [3,4]^2, scattering elsewhere;
+  * heterogeneous batch / closure instances: random 8x8 piecewise-constant
+    materials with a Gaussian source (no counterpart in the paper; the recipe
+    is stated in the design notes).
+Moment index 0 is the zeroth moment R_0^0 (the paper's first component).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Dict, Optional, Sequence
+
+import numpy as np
+
+Field = Callable[[float, np.ndarray, np.ndarray], np.ndarray]
+
+BC_PERIODIC = "periodic"
+BC_EXTRAPOLATION = "extrapolation"
+
+
+@dataclasses.dataclass
+class Problem:
+    """Problem statement (the paper's ``par`` struct, Sect. 5.1)."""
+
+    name: str
+    N: int                       # moment order
+    n: tuple                     # (nx, ny) cells
+    ax: tuple                    # (x0, x1, y0, y1)
+    bc: tuple                    # per axis: BC_PERIODIC or BC_EXTRAPOLATION
+    cfl: float
+    t_final: float
+    sigma_a: Field
+    sigma_s0: Field
+    # anisotropic part: sigma_sl(l, t, x, y) for l >= 1, or None (isotropic)
+    sigma_sl: Optional[Callable[[int, float, np.ndarray, np.ndarray], np.ndarray]] = None
+    source: Dict[int, Field] = dataclasses.field(default_factory=dict)
+    initial: Dict[int, Field] = dataclasses.field(default_factory=dict)
+    time_dependent: bool = False  # materials / sources depend on t
+    precision: str = "fp64"
+    seed: Optional[int] = None
+
+    @property
+    def nmom(self) -> int:
+        return (self.N + 1) * (self.N + 2) // 2
+
+
+def _const(v: float) -> Field:
+    def f(t, x, y):
+        return np.full(np.broadcast(x, y).shape, float(v))
+    return f
+
+
+def _zero(t, x, y):
+    return np.zeros(np.broadcast(x, y).shape)
+
+
+def gaussian_std(s: float, xc: float = 0.0, yc: float = 0.0) -> Field:
+    """Unit-mass isotropic Gaussian of standard deviation s."""
+    def f(t, x, y):
+        r2 = (np.asarray(x) - xc) ** 2 + (np.asarray(y) - yc) ** 2
+        return np.exp(-r2 / (2.0 * s * s)) / (2.0 * math.pi * s * s)
+    return f
+
+
+def gaussian_pseudo_time(sigma: float) -> Field:
+    """The paper's Gaussian written with a pseudo-time sigma (Sect. 6.4):
+    1/(4 pi sigma) exp(-r^2 / (4 sigma))."""
+    def f(t, x, y):
+        r2 = np.asarray(x) ** 2 + np.asarray(y) ** 2
+        return np.exp(-r2 / (4.0 * sigma)) / (4.0 * math.pi * sigma)
+    return f
+
+
+# --------------------------------------------------------------------------
+# Line source (Sect. 6.4), synthetic sizes of the benchmark configurations.
+# --------------------------------------------------------------------------
+def line_source(N: int = 3, n: int = 100, s: float = 0.03, half_width: float = 1.5,
+                t_final: float = 1.0, cfl: float = 0.5, precision: str = "fp64",
+                bc: str = BC_EXTRAPOLATION) -> Problem:
+    return Problem(
+        name=f"line_source_P{N}_{n}",
+        N=N, n=(n, n), ax=(-half_width, half_width, -half_width, half_width),
+        bc=(bc, bc), cfl=cfl, t_final=t_final,
+        sigma_a=_zero, sigma_s0=_const(1.0),
+        initial={0: gaussian_std(s)}, precision=precision)
+
+
+# --------------------------------------------------------------------------
+# Checkerboard lattice (Sect. 6.3).  Unit block (i, j) covers [i, i+1) x [j, j+1).
+# Absorbers: i, j in 1..5 with i + j even, except the source block (3, 3) and
+# the open block (3, 5) above it: eleven absorbing unit squares.
+# --------------------------------------------------------------------------
+CHECKER_ABSORBERS = tuple(
+    (i, j) for i in range(1, 6) for j in range(1, 6)
+    if (i + j) % 2 == 0 and (i, j) not in ((3, 3), (3, 5)))
+
+
+def _block_index(v: np.ndarray) -> np.ndarray:
+    # points that lie on a block edge belong to the block above (half-open
+    # blocks); the small offset absorbs round-off in the sampled coordinate
+    return np.floor(np.asarray(v, dtype=np.float64) + 1e-9).astype(np.int64)
+
+
+def _checker_absorber_mask(x, y):
+    bi, bj = _block_index(x), _block_index(y)
+    m = np.zeros(np.broadcast(bi, bj).shape, dtype=bool)
+    for (i, j) in CHECKER_ABSORBERS:
+        m |= (bi == i) & (bj == j)
+    return m
+
+
+def checkerboard(N: int = 7, n: int = 280, t_final: float = 3.2, cfl: float = 0.5,
+                 precision: str = "fp64") -> Problem:
+    def sig_a(t, x, y):
+        return np.where(_checker_absorber_mask(x, y), 10.0, 0.0)
+
+    def sig_s(t, x, y):
+        return np.where(_checker_absorber_mask(x, y), 0.0, 1.0)
+
+    def src(t, x, y):
+        bi, bj = _block_index(x), _block_index(y)
+        return np.where((bi == 3) & (bj == 3), 1.0, 0.0)
+
+    return Problem(
+        name=f"checkerboard_P{N}_{n}", N=N, n=(n, n), ax=(0.0, 7.0, 0.0, 7.0),
+        bc=(BC_EXTRAPOLATION, BC_EXTRAPOLATION), cfl=cfl, t_final=t_final,
+        sigma_a=sig_a, sigma_s0=sig_s, source={0: src}, precision=precision)
+
+
+# --------------------------------------------------------------------------
+# Random heterogeneous instances (batched solves and the learned closure).
+# Domain [-1,1]^2, extrapolation; 8x8 blocks of width 0.25 with sigma_a and
+# sigma_s log-uniform in [0.1, 10]; isotropic Gaussian source
+# exp(-|x - xc|^2 / (2 s^2)), xc ~ U([-0.5,0.5]^2), s ~ U(0.05, 0.2); zero IC.
+# --------------------------------------------------------------------------
+BATCH_SEED0 = 12112205
+CLOSURE_SEED0 = 1_000_000
+
+
+def _block_field(values: np.ndarray, x0: float, width: float) -> Field:
+    nb = values.shape[0]
+
+    def f(t, x, y):
+        bi = np.clip(np.floor((np.asarray(x) - x0) / width + 1e-9).astype(np.int64), 0, nb - 1)
+        bj = np.clip(np.floor((np.asarray(y) - x0) / width + 1e-9).astype(np.int64), 0, nb - 1)
+        return values[bj, bi]
+    return f
+
+
+def random_medium(seed: int, N: int, n: int, t_final: float = 0.5, cfl: float = 0.5,
+                  precision: str = "fp32") -> Problem:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sa = 10.0 ** rng.uniform(-1.0, 1.0, size=(8, 8))
+    ss = 10.0 ** rng.uniform(-1.0, 1.0, size=(8, 8))
+    xc, yc = rng.uniform(-0.5, 0.5, size=2)
+    s = rng.uniform(0.05, 0.2)
+
+    def src(t, x, y):
+        r2 = (np.asarray(x) - xc) ** 2 + (np.asarray(y) - yc) ** 2
+        return np.exp(-r2 / (2.0 * s * s))
+
+    return Problem(
+        name=f"random_medium_s{seed}_P{N}_{n}", N=N, n=(n, n), ax=(-1.0, 1.0, -1.0, 1.0),
+        bc=(BC_EXTRAPOLATION, BC_EXTRAPOLATION), cfl=cfl, t_final=t_final,
+        sigma_a=_block_field(sa, -1.0, 0.25), sigma_s0=_block_field(ss, -1.0, 0.25),
+        source={0: src}, precision=precision, seed=seed)
+
+
+def batch_instance(i: int, precision: str = "fp32") -> Problem:
+    """Instance i of the 256-instance heterogeneous batch: side n ~ U{64..512},
+    N ~ U{3,5,7,9}, drawn from the instance's own seed."""
+    seed = BATCH_SEED0 + i
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rng.integers(64, 513))
+    N = int(rng.choice([3, 5, 7, 9]))
+    return random_medium(seed + 7_000_000, N, n, precision=precision)
+
+
+def batch(count: int = 256, precision: str = "fp32") -> Sequence[Problem]:
+    return [batch_instance(i, precision) for i in range(count)]
+
+
+def closure_instance(k: int, N: int, n: int = 256, precision: str = "fp32") -> Problem:
+    """Closure training (k < 2000) and held-out evaluation (k >= 2000) instance."""
+    return random_medium(CLOSURE_SEED0 + k, N, n, precision=precision)
+
+
+# --------------------------------------------------------------------------
+# The benchmark configurations by name.
+# --------------------------------------------------------------------------
+def config(name: str, precision: Optional[str] = None) -> Problem:
+    if name == "c1":
+        return line_source(N=3, n=100, s=0.03, precision=precision or "fp64")
+    if name == "c2":
+        return checkerboard(N=7, n=280, precision=precision or "fp64")
+    if name == "c3":
+        return line_source(N=39, n=1000, s=0.01, precision=precision or "fp32")
+    raise KeyError(name)
+
+
+def random_state(seed: int, shapes: Sequence[tuple]) -> list:
+    """Seeded random moment planes (for parity tests that start from a rough state)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [rng.standard_normal(s) for s in shapes]
