@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Throughput of the staggered-grid P_N step on one MI355X.
+
+Default workload: the large line source (P_39, 820 moments, 1000 x 1000
+cells, FP32 storage, CFL 0.5, t_final = 1: 666 steps).  A step is one full
+time step of every moment (odd and even parity sweeps); the first `warmup`
+steps of the run are untimed and the remaining `steps` are timed, so the
+default covers exactly the run to t_final.
+
+Prints one JSON line: cell-moment updates/s (nx * ny * moments * steps /
+wall time of the timed steps), the sweep kernel's achieved algorithmic HBM
+bandwidth against the 8 TB/s peak (HIP events around every launch, on the
+stream the kernels run on), and the oracle's throughput on a bounded sample
+of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_line_source_P39_1000_fp32_pmc.json")
+SWEEP_SRC = os.path.join(ROOT, "paper_1211_2205_amd", "csrc", "sweep.hip")
+
+
+def _sweep_source_hash():
+    with open(SWEEP_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(launch_bytes, precision):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on
+    the current sweep kernel source; else None."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sweep_source_sha256_16") != _sweep_source_hash() or rec.get("precision") != precision:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(prob, rows):
+    """Oracle (FP64, plain C + OpenMP) on a band of `rows` grid rows of the same
+    workload for one full step."""
+    import workloads as wl
+    from oracle.scheme import OracleSolver
+    h = (prob.ax[1] - prob.ax[0]) / prob.n[0]
+    band = wl.line_source(N=prob.N, n=prob.n[0], s=0.01, precision="fp64")
+    band.n = (prob.n[0], rows)
+    band.ax = (prob.ax[0], prob.ax[1], -rows * h / 2, rows * h / 2)
+    o = OracleSolver(band)
+    o.evaluate_materials(0.0)
+    t0 = time.perf_counter()
+    o.step()
+    t1 = time.perf_counter()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    updates = prob.n[0] * rows * o.nmom
+    return {"value": updates / (t1 - t0), "unit": "cell-moment updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one full step (4 half-steps) of P_{prob.N} on a {prob.n[0]} x {rows} band "
+                      f"({updates:.3e} cell-moment updates, {t1 - t0:.1f} s, FP64)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the rest of the run)")
+    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--variant", type=int, default=None, help="sweep tile variant (default: autotune)")
+    ap.add_argument("--cpu-rows", type=int, default=200, help="rows of the oracle's CPU sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="only run a device copy of this size (HBM counter calibration) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design note, not code)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    if args.copy_calibration_gib > 0:
+        n = int(args.copy_calibration_gib * 2 ** 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+
+    import paper_1211_2205_amd as pa
+    import workloads as wl
+
+    prob = wl.config(args.config, precision=args.precision)
+    prec = prob.precision
+    s = pa.Solver.from_problem(prob)
+    s.bind_torch()
+    if args.variant is None:
+        s.autotune(2)
+    else:
+        s.set_variant(args.variant)
+    total = s.nsteps
+    warm = max(0, min(args.warmup, total - 1))
+    steps = args.steps if args.steps is not None else total - warm
+    nmom = s.nmom
+    nx, ny = prob.n
+
+    s.advance(warm)
+    s.synchronize()
+    torch.cuda.synchronize()
+    s.profile_begin()
+    t0 = time.perf_counter()
+    s.advance(steps)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms, launches, alg_bytes = s.profile_end()
+    wall = t1 - t0
+    diag = s.diagnostics()
+
+    updates = nx * ny * nmom * steps
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    per_launch = alg_bytes / launches
+    v, tx, ty = s.variant()
+    traffic = _traffic(per_launch, prec)
+    out = {
+        "metric": "cell-moment updates/s",
+        "value": updates / wall,
+        "unit": "cell-moment updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec],
+        "data": "synthetic",
+        "config": {"workload": f"{prob.name}_{prec}", "N": prob.N, "moments": nmom, "cells": [nx, ny],
+                   "t_final": prob.t_final, "steps_to_t_final": total, "tile": [tx, ty],
+                   "sweeps_timed": launches},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "sweep_kernel", "avg_launch_ms": kernel_ms / launches,
+                     "algorithmic_bytes_per_launch": per_launch},
+        "state_check": {"mass": diag["mass"], "l2": diag["l2"], "nonfinite": diag["nonfinite"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

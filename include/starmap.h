@@ -1,0 +1,233 @@
+/*
+ * starmap.h -- C ABI of the MI355X staggered-grid P_N solver.
+ *
+ * The library advances the 2D real spherical-harmonics P_N equations of
+ * radiative transfer,
+ *     d_t u + M_x d_x u + M_y d_y u + C u = q,
+ * with the staggered-grid scheme of Seibold & Frank, "StaRMAP - A second order
+ * staggered grid method for spherical harmonics moment equations of radiative
+ * transfer" (arXiv 1211.2205):
+ *   - the (N+1)(N+2)/2 real moments R_l^m, I_l^m (Sect. 3) live on four mutually
+ *     staggered grids G11, G21, G12, G22 (Sect. 4.1, eqs. grid11 and
+ *     staggered_grids);
+ *   - D_x, D_y are half-cell central differences (eq. central_differences);
+ *   - boundaries are periodic or constant extrapolation (Sect. 4.2);
+ *   - a time step is the Strang composition S^o S^e S^e S^o of exact sub-step
+ *     solutions u <- u + tau (r - c u) E(-c tau), E(z) = (e^z - 1)/z
+ *     (Sect. 4.3, eqs. sub_step_solution and solution_operator_full_step).
+ *
+ * Conventions for every call below:
+ *   - Functions returning int give STARMAP_OK (0) or a negative STARMAP_E*
+ *     code; no C++ exception crosses the ABI.  starmap_last_error() returns a
+ *     message for the last failure on the calling thread (owned by the
+ *     library, valid until the next failing call on that thread).
+ *   - Handles are opaque; the caller creates and destroys them.
+ *   - Host arrays passed in are copied; the caller keeps ownership.
+ *   - Moment index k follows the paper's order: l ascending; within l, m
+ *     descending; R_l^m before I_l^m (I exists for m > 0).  Index 0 is R_0^0.
+ *   - A moment's values are laid out on its own grid, x fastest:
+ *       cell-centred axis: nc = n points at x0 + (i + 1/2) h, i = 0..n-1;
+ *       nodal axis:        nc = n + 1 - p points at x0 + (i + p) h, i = 0..nc-1,
+ *     where p = 1 for a periodic axis (node 0 coincides with node n and only
+ *     nodes 1..n are stored) and p = 0 for extrapolation.
+ *   - Device memory is owned by the library unless the caller binds its own
+ *     (starmap_bind_device); all device work runs on the bound stream (the
+ *     null stream otherwise) and the blocking calls synchronise it.
+ */
+#ifndef STARMAP_H
+#define STARMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STARMAP_OK 0
+#define STARMAP_EINVAL (-1)    /* invalid argument or problem description */
+#define STARMAP_ENOMEM (-2)    /* host or device allocation failed / workspace too small */
+#define STARMAP_EHIP (-3)      /* a HIP runtime call failed */
+#define STARMAP_EUNSTABLE (-4) /* non-finite values found by the diagnostics */
+#define STARMAP_ESTATE (-5)    /* call not valid in the solver's current state */
+
+/* Boundary type per axis (Sect. 4.2; the periodicity flag p of eq.
+   periodicity_flags is 1 for STARMAP_BC_PERIODIC and 0 otherwise). */
+#define STARMAP_BC_PERIODIC 0
+#define STARMAP_BC_EXTRAPOLATION 1
+
+/* Storage precision of the moments.  FP64 computes in FP64; FP32 and BF16
+   store in that type and compute in FP32. */
+#define STARMAP_FP64 0
+#define STARMAP_FP32 1
+#define STARMAP_BF16 2
+
+/* Closure of the moment hierarchy: plain P_N truncation, or P_N plus the
+   learned correction of the highest order (starmap_closure_load). */
+#define STARMAP_CLOSURE_PN 0
+#define STARMAP_CLOSURE_LEARNED 1
+
+/* Field selectors of starmap_set_field_array. */
+#define STARMAP_FIELD_ABSORPTION 0 /* sigma_a on moment k's grid  */
+#define STARMAP_FIELD_SCATTERING 1 /* sigma_s0 on moment k's grid */
+#define STARMAP_FIELD_SOURCE 2     /* q_k on moment k's grid      */
+#define STARMAP_FIELD_INITIAL 3    /* u_k(t = 0)                  */
+
+/* Problem statement (the paper's par struct, Sect. 5.1). */
+typedef struct {
+  double ax[4];      /* domain x0, x1, y0, y1 */
+  int32_t n[2];      /* cells nx, ny (>= 2 each) */
+  int32_t bc[2];     /* STARMAP_BC_* per axis */
+  int32_t N;         /* moment order, 0 < N <= 99 */
+  double cfl;        /* dt0 = cfl * min(dx, dy) / rho(M_x); stable for cfl < 1/sqrt(2) */
+  double t_final;    /* final time; the step count is rounded up to land on it */
+  int32_t precision; /* STARMAP_FP64 | STARMAP_FP32 | STARMAP_BF16 */
+  int32_t closure;   /* STARMAP_CLOSURE_PN | STARMAP_CLOSURE_LEARNED */
+} starmap_problem;
+
+typedef struct starmap_solver starmap_solver;
+
+/* Vectorised field callback: write f(t, x[i], y[i]) into out[i] for
+   i = 0..count-1 (physical coordinates).  Return 0 on success; any other value
+   aborts the calling function with STARMAP_EINVAL. */
+typedef int (*starmap_field_fn)(void* ctx, double t, int64_t count, const double* x,
+                                const double* y, double* out);
+
+/* ---------------------------------------------------------------- host-only
+   These need no GPU. */
+
+/* Number of moments (N+1)(N+2)/2 (Sect. 3, 2D reduction). */
+int starmap_num_moments(int32_t N);
+
+/* Moment k of order N: is_imag (0: R_l^m, 1: I_l^m), l, m, and its grid
+   G_{gx gy} (1 = cell-centred, 2 = nodal along that axis; Lemma 2 and
+   eq. matrix_conditions).  Any output pointer may be NULL. */
+int starmap_moment_info(int32_t N, int32_t k, int32_t* is_imag, int32_t* l, int32_t* m,
+                        int32_t* gx, int32_t* gy);
+
+/* Rows of the real moment matrix M_x (axis 0) or M_y (axis 1) of order N
+   (Sect. 3, M^real = S M^complex S^-1; symmetric, at most 4 nonzeros a row).
+   cols and vals hold 4 * num_moments entries (row-major, 4 slots per row);
+   unused slots get col = -1 and val = 0. */
+int starmap_closure_pn(int32_t N, int32_t axis, int32_t* cols, double* vals);
+
+/* Largest eigenvalue magnitude of M_x of order N (the maximal wave speed that
+   scales the admissible time step, Sect. 4.6 and Sect. 5.3). */
+int starmap_spectral_radius(int32_t N, double* rho);
+
+/* ------------------------------------------------------------- solver setup */
+
+/* Validate the problem, build the plan (moment matrices, grid classes, rho,
+   dt, step count).  Allocates no device memory. */
+int starmap_create(const starmap_problem* prob, starmap_solver** out);
+void starmap_destroy(starmap_solver* s);
+
+/* Material and source fields, sampled on the host in FP64 at each grid's
+   points when the solver first needs them (Sect. 5.6).  Isotropic scattering
+   uses sigma_s0 only: moments of order l >= 1 decay with sigma_a + sigma_s0,
+   the zeroth moment with sigma_a (Sect. 2: Sigma_tl = Sigma_a + Sigma_s0 -
+   Sigma_sl).  Missing fields are zero.  time_dependent != 0 re-samples the
+   field at t + dt/2 before every step. */
+int starmap_set_absorption(starmap_solver* s, starmap_field_fn f, void* ctx, int32_t time_dependent);
+int starmap_set_scattering(starmap_solver* s, starmap_field_fn f, void* ctx, int32_t time_dependent);
+/* Anisotropic part: sigma_sl(l, t, x, y) for l >= 1 via one callback per order
+   (ctx receives the order through the callback's own state).  Optional. */
+int starmap_set_scattering_order(starmap_solver* s, int32_t l, starmap_field_fn f, void* ctx,
+                                 int32_t time_dependent);
+/* Source q_k of moment k (isotropic sources act on k = 0 only). */
+int starmap_set_source(starmap_solver* s, int32_t k, starmap_field_fn f, void* ctx, int32_t time_dependent);
+/* Initial value u_k(0) of moment k (others start at 0). */
+int starmap_set_initial(starmap_solver* s, int32_t k, starmap_field_fn f, void* ctx);
+
+/* Pre-sampled variant: host_vals holds moment k's grid layout (see above).
+   ABSORPTION/SCATTERING accept any k and define the field on that moment's
+   grid; they are time-independent. */
+int starmap_set_field_array(starmap_solver* s, int32_t which, int32_t k, const double* host_vals);
+
+/* Grid of moment k: points along x and y, and the coordinates of its first
+   point. */
+int starmap_moment_shape(const starmap_solver* s, int32_t k, int32_t* nx_k, int32_t* ny_k,
+                         double* x0_k, double* y0_k);
+
+/* Time bookkeeping: current time, step, steps done, steps to t_final. */
+int starmap_time(const starmap_solver* s, double* t, double* dt, int64_t* steps_done,
+                 int64_t* steps_total);
+
+/* ------------------------------------------------------------ device memory */
+
+/* Bytes of device workspace the solver needs (state planes, material and
+   source planes, sweep programs, diagnostics scratch), 256-byte aligned. */
+int starmap_workspace_bytes(const starmap_solver* s, size_t* bytes);
+
+/* Use caller-owned device memory (at least starmap_workspace_bytes, 256-byte
+   aligned) and a caller-owned HIP stream (hipStream_t, or NULL for the null
+   stream).  Must precede the first device call; the memory must outlive the
+   solver.  Without it the library allocates its own on first use. */
+int starmap_bind_device(starmap_solver* s, void* dev_ptr, size_t bytes, void* hip_stream);
+
+/* ------------------------------------------------------------------- running */
+
+/* Advance nsteps full steps (S^o_{dt/2} S^e_{dt/2} S^e_{dt/2} S^o_{dt/2} each).
+   Time-independent data: the device runs S^o_{dt/2}, [S^e_{dt}, S^o_{dt}]^{n-1},
+   S^e_{dt}, S^o_{dt/2}, equal in exact arithmetic (two exact half-steps with
+   frozen data compose to one exact full step).  Time-dependent data is
+   re-sampled at t + dt/2 and each step runs S^o_{dt/2} S^e_{dt} S^o_{dt/2}.
+   The call returns after queueing the work on the stream (asynchronous). */
+int starmap_advance(starmap_solver* s, int64_t nsteps);
+
+/* Advance to t_final and synchronise. */
+int starmap_run(starmap_solver* s);
+
+/* Queue nsweeps single parity sweeps with sub-step tau (parity 0 even, 1 odd),
+   for profiling of the sweep kernel; does not change the time bookkeeping. */
+int starmap_sweep(starmap_solver* s, int32_t parity, double tau, int32_t nsweeps);
+
+/* Synchronise the solver's stream. */
+int starmap_synchronize(starmap_solver* s);
+
+/* Copy moment k at the current time to host_out (moment k's grid layout,
+   FP64) and synchronise. */
+int starmap_get_moment(const starmap_solver* s, int32_t k, double* host_out);
+
+/* Checkpoint: the raw state (opaque, starmap_state_bytes long) plus the time
+   bookkeeping.  Restoring into a solver created from the same problem and
+   continuing with the same advance calls reproduces the uninterrupted run bit
+   for bit. */
+int starmap_state_bytes(const starmap_solver* s, size_t* bytes);
+int starmap_get_state(const starmap_solver* s, void* host_buf, size_t bytes, double* t, int64_t* step);
+int starmap_set_state(starmap_solver* s, const void* host_buf, size_t bytes, double t, int64_t step);
+
+/* FP64 reductions on the device: mass dx*dy*sum(R_0^0), discrete L2 norm
+   (dx*dy*sum_k sum u_k^2)^(1/2) (eq. discrete_L2_norm), max |u|, and the count
+   of non-finite values.  Returns STARMAP_EUNSTABLE if that count is nonzero
+   (the outputs are still written).  Any output pointer may be NULL. */
+int starmap_diagnostics(const starmap_solver* s, double* mass_r00, double* l2, double* maxabs,
+                        int32_t* nonfinite);
+
+/* Tile variant of the sweep kernel: -1 chooses by the autotuner (default).
+   starmap_autotune times every variant that fits on a few sweeps of this
+   solver, keeps the fastest and writes it to the cache file named by the
+   environment variable STARMAP_TUNE_CACHE (if set). */
+int starmap_set_variant(starmap_solver* s, int32_t variant);
+int starmap_get_variant(const starmap_solver* s, int32_t* variant, int32_t* tile_x, int32_t* tile_y);
+int starmap_autotune(starmap_solver* s, int32_t sweeps_per_variant);
+
+/* Bytes the sweep kernel moves per parity sweep by the algorithm's count:
+   every input plane read once, every output plane read and written once, plus
+   the decay and source planes it reads (valid points only). */
+int starmap_sweep_bytes(const starmap_solver* s, int32_t parity, double* bytes);
+
+/* Per-launch timing of the sweep kernel: between begin and end every sweep
+   launch is bracketed by HIP events recorded on the solver's stream.  end
+   synchronises and returns the summed kernel time (ms), the number of
+   launches, and their summed algorithmic bytes (starmap_sweep_bytes). */
+int starmap_profile_begin(starmap_solver* s);
+int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches, double* bytes);
+
+const char* starmap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STARMAP_H */

@@ -1,0 +1,1056 @@
+// C ABI of the staggered-grid P_N solver: problem setup, host sampling of the
+// fields, device workspace, time stepping, checkpoints and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/starmap.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace starmap;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(STARMAP_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct FieldSource {
+  starmap_field_fn fn = nullptr;
+  void* ctx = nullptr;
+  bool time_dependent = false;
+  // pre-sampled values on grid g = (gx-1) + 2 (gy-1), public layout
+  std::array<std::vector<double>, 4> arrays;
+  bool has_array[4] = {false, false, false, false};
+  bool set() const { return fn || has_array[0] || has_array[1] || has_array[2] || has_array[3]; }
+};
+
+int grid_id(int gx, int gy) { return (gx - 1) + 2 * (gy - 1); }
+
+}  // namespace
+
+struct starmap_solver {
+  starmap_problem prob{};
+  int N = 0, nmom = 0;
+  std::vector<MomentInfo> moms;
+  std::vector<CouplingRow> rows;
+  double rho = 0, dx = 0, dy = 0, dt = 0;
+  int64_t steps_total = 0, steps_done = 0;
+  double t = 0;
+  int nx = 0, ny = 0, px = 0, py = 0;
+  int storage = STORE_FP64;
+  size_t ssize = 8, csize = 8;
+  int pitch = 0, nrows = 0;
+  int64_t plane_stride = 0;
+
+  FieldSource absorption, scattering;
+  std::map<int, FieldSource> scattering_order;  // l -> sigma_sl
+  std::map<int, FieldSource> source;            // k -> q_k
+  std::map<int, FieldSource> initial;           // k -> u_k(0)
+  bool anisotropic = false;
+  bool time_dependent = false;
+
+  DecayMap dmap;
+  std::vector<int32_t> qk;  // per moment: source plane or -1
+  int nsrc = 0;
+
+  // device
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  bool owns_dev = false;
+  bool owns_stream = false;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  size_t off_state = 0, off_decay = 0, off_src = 0, off_prog[2] = {0, 0}, off_diag = 0;
+  size_t prog_bytes[2] = {0, 0};
+  int diag_rows_per_block = 64, diag_nblocks = 0;
+
+  bool device_ready = false;     // workspace allocated and state uploaded
+  bool materials_ready = false;  // decay and source planes uploaded for current time
+  int variant = -1;              // -1: not chosen yet
+  int slots = 0;
+  SweepProgram prog[2];
+  bool prog_uploaded = false;
+
+  // per-launch HIP events of the sweep kernel (starmap_profile_begin/end)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double prof_bytes = 0.0;
+  double sweep_bytes_cache[2] = {-1.0, -1.0};
+
+  // plane_stride is a multiple of 128 elements, so planes of every element
+  // size start 256-byte aligned and state and material planes share one
+  // element stride
+  size_t plane_bytes_state() const { return size_t(plane_stride) * ssize; }
+  size_t plane_bytes_c() const { return size_t(plane_stride) * csize; }
+};
+
+namespace {
+
+int points_x(const starmap_solver* s, int gx) { return gx == AXIS_CELL ? s->nx : s->nx + 1 - s->px; }
+int points_y(const starmap_solver* s, int gy) { return gy == AXIS_CELL ? s->ny : s->ny + 1 - s->py; }
+
+// Internal storage index of public index a along an axis: nodes of a periodic
+// axis are stored modulo n (node n, the last public node, lands on index 0).
+int internal_x(const starmap_solver* s, int gx, int a) {
+  return (gx == AXIS_NODE && s->px) ? (a + 1) % s->nx : a;
+}
+int internal_y(const starmap_solver* s, int gy, int b) {
+  return (gy == AXIS_NODE && s->py) ? (b + 1) % s->ny : b;
+}
+
+void grid_coords(const starmap_solver* s, int gx, int gy, std::vector<double>& X, std::vector<double>& Y) {
+  const int nxk = points_x(s, gx), nyk = points_y(s, gy);
+  X.resize(size_t(nxk) * nyk);
+  Y.resize(size_t(nxk) * nyk);
+  for (int b = 0; b < nyk; ++b) {
+    const double y = gy == AXIS_CELL ? s->prob.ax[2] + (b + 0.5) * s->dy : s->prob.ax[2] + (b + s->py) * s->dy;
+    for (int a = 0; a < nxk; ++a) {
+      const double x = gx == AXIS_CELL ? s->prob.ax[0] + (a + 0.5) * s->dx : s->prob.ax[0] + (a + s->px) * s->dx;
+      X[size_t(b) * nxk + a] = x;
+      Y[size_t(b) * nxk + a] = y;
+    }
+  }
+}
+
+// Sample a field on grid (gx, gy) at time t (public layout); zero if unset.
+int sample(const starmap_solver* s, const FieldSource& f, int gx, int gy, double t, std::vector<double>& out) {
+  const int g = grid_id(gx, gy);
+  const size_t n = size_t(points_x(s, gx)) * points_y(s, gy);
+  if (f.has_array[g]) {
+    out = f.arrays[g];
+    return STARMAP_OK;
+  }
+  out.assign(n, 0.0);
+  if (!f.fn) return STARMAP_OK;
+  std::vector<double> X, Y;
+  grid_coords(s, gx, gy, X, Y);
+  if (f.fn(f.ctx, t, int64_t(n), X.data(), Y.data(), out.data()) != 0)
+    return fail(STARMAP_EINVAL, "field callback reported an error");
+  return STARMAP_OK;
+}
+
+template <typename T>
+void to_type(double v, T* out) { *out = T(v); }
+void to_type(double v, uint16_t* out) {
+  float f = float(v);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) { *out = uint16_t((u >> 16) | 0x40u); return; }
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  *out = uint16_t(u >> 16);
+}
+double from_type(double v) { return v; }
+double from_type(float v) { return v; }
+double from_type(uint16_t v) {
+  uint32_t u = uint32_t(v) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Scatter a public-layout plane into a padded internal plane of type T.
+template <typename T>
+void scatter_plane(const starmap_solver* s, int gx, int gy, const double* vals, std::vector<T>& buf) {
+  buf.assign(size_t(s->plane_stride), T(0));
+  const int nxk = points_x(s, gx), nyk = points_y(s, gy);
+  for (int b = 0; b < nyk; ++b) {
+    const int Yi = internal_y(s, gy, b);
+    for (int a = 0; a < nxk; ++a) {
+      const int Xi = internal_x(s, gx, a);
+      to_type(vals[size_t(b) * nxk + a], &buf[size_t(Yi) * s->pitch + Xi]);
+    }
+  }
+}
+
+template <typename T>
+void gather_plane(const starmap_solver* s, int gx, int gy, const T* buf, double* out) {
+  const int nxk = points_x(s, gx), nyk = points_y(s, gy);
+  for (int b = 0; b < nyk; ++b) {
+    const int Yi = internal_y(s, gy, b);
+    for (int a = 0; a < nxk; ++a) {
+      out[size_t(b) * nxk + a] = from_type(buf[size_t(Yi) * s->pitch + internal_x(s, gx, a)]);
+    }
+  }
+}
+
+int upload_plane(starmap_solver* s, void* dst, int gx, int gy, const double* vals, bool compute_type) {
+  const int kind = compute_type ? (s->storage == STORE_FP64 ? 0 : 1) : s->storage;
+  if (kind == STORE_FP64) {
+    std::vector<double> buf;
+    scatter_plane(s, gx, gy, vals, buf);
+    HIP_TRY(hipMemcpyAsync(dst, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else if (kind == STORE_FP32) {
+    std::vector<float> buf;
+    scatter_plane(s, gx, gy, vals, buf);
+    HIP_TRY(hipMemcpyAsync(dst, buf.data(), buf.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else {
+    std::vector<uint16_t> buf;
+    scatter_plane(s, gx, gy, vals, buf);
+    HIP_TRY(hipMemcpyAsync(dst, buf.data(), buf.size() * 2, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return STARMAP_OK;
+}
+
+char* dptr(const starmap_solver* s, size_t off) { return static_cast<char*>(s->dev) + off; }
+
+void layout(starmap_solver* s) {
+  // decay planes and source planes
+  s->dmap = decay_map(s->N, s->anisotropic);
+  s->qk.assign(s->nmom, -1);
+  s->nsrc = 0;
+  for (auto& kv : s->source)
+    if (kv.second.set()) s->qk[kv.first] = s->nsrc++;
+  // program sizes do not depend on the tile variant
+  for (int p = 0; p < 2; ++p) {
+    s->prog[p] = build_sweep_program(s->N, p, 64, 4, s->dx, s->dy, s->rows, s->dmap, s->qk);
+    const auto& pr = s->prog[p];
+    s->prog_bytes[p] = align256(pr.orders.size() * 16) + align256(pr.loads.size() * 16) +
+                       align256(pr.outs.size() * 32) + align256(pr.terms.size() * 8) +
+                       align256(pr.coefs.size() * s->csize);
+  }
+  s->slots = s->prog[0].slots;
+  size_t off = 0;
+  s->off_state = off;
+  off += size_t(s->nmom) * s->plane_bytes_state();
+  s->off_decay = off;
+  off += size_t(s->dmap.nplanes) * s->plane_bytes_c();
+  s->off_src = off;
+  off += size_t(std::max(s->nsrc, 1)) * s->plane_bytes_c();
+  for (int p = 0; p < 2; ++p) {
+    s->off_prog[p] = off;
+    off += s->prog_bytes[p];
+  }
+  s->off_diag = off;
+  int max_rows = s->ny + 1;
+  s->diag_nblocks = diag_blocks(s->nmom, max_rows, s->diag_rows_per_block);
+  off += align256(size_t(s->diag_nblocks) * 4 * 8) + 256 + align256(size_t(s->nmom) * 8);
+  s->dev_bytes = off;
+}
+
+int upload_program(starmap_solver* s) {
+  const TileShape ts = sweep_variant(s->variant);
+  for (int p = 0; p < 2; ++p) {
+    s->prog[p] = build_sweep_program(s->N, p, ts.tx, ts.ty, s->dx, s->dy, s->rows, s->dmap, s->qk);
+    const auto& pr = s->prog[p];
+    std::vector<char> buf(s->prog_bytes[p], 0);
+    size_t o = 0;
+    std::vector<int32_t> ords, loads, outs, terms;
+    for (auto& x : pr.orders) { ords.insert(ords.end(), {x.load0, x.load1, x.out0, x.out1}); }
+    for (auto& x : pr.loads) { loads.insert(loads.end(), {x.k, x.lds, x.ox, x.oy}); }
+    for (auto& x : pr.outs) {
+      outs.insert(outs.end(), {x.k, x.gslot, x.gx, x.gy, x.dk, x.qk, x.nterms, x.term0});
+    }
+    for (auto& x : pr.terms) { terms.insert(terms.end(), {x.off, x.stride}); }
+    std::memcpy(buf.data() + o, ords.data(), ords.size() * 4);
+    o += align256(pr.orders.size() * 16);
+    std::memcpy(buf.data() + o, loads.data(), loads.size() * 4);
+    o += align256(pr.loads.size() * 16);
+    std::memcpy(buf.data() + o, outs.data(), outs.size() * 4);
+    o += align256(pr.outs.size() * 32);
+    std::memcpy(buf.data() + o, terms.data(), terms.size() * 4);
+    o += align256(pr.terms.size() * 8);
+    if (s->csize == 8) {
+      std::memcpy(buf.data() + o, pr.coefs.data(), pr.coefs.size() * 8);
+    } else {
+      std::vector<float> cf(pr.coefs.begin(), pr.coefs.end());
+      std::memcpy(buf.data() + o, cf.data(), cf.size() * 4);
+    }
+    HIP_TRY(hipMemcpyAsync(dptr(s, s->off_prog[p]), buf.data(), buf.size(), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  s->prog_uploaded = true;
+  return STARMAP_OK;
+}
+
+int ensure_stream(starmap_solver* s) {
+  if (!s->bound && !s->stream && !s->owns_stream) {
+    HIP_TRY(hipStreamCreate(&s->stream));
+    s->owns_stream = true;
+  }
+  return STARMAP_OK;
+}
+
+int upload_materials(starmap_solver* s, double t_eval) {
+  // decay planes: c = sigma_a (zeroth moment), sigma_a + sigma_s0 - sigma_sl (l >= 1)
+  std::map<int, std::vector<double>> sa, ss;
+  auto get = [&](std::map<int, std::vector<double>>& cache, const FieldSource& f, int gx, int gy,
+                 std::vector<double>** out) -> int {
+    int g = grid_id(gx, gy);
+    auto it = cache.find(g);
+    if (it == cache.end()) {
+      std::vector<double> v;
+      int rc = sample(s, f, gx, gy, t_eval, v);
+      if (rc) return rc;
+      it = cache.emplace(g, std::move(v)).first;
+    }
+    *out = &it->second;
+    return STARMAP_OK;
+  };
+  for (int p = 0; p < s->dmap.nplanes; ++p) {
+    const int gx = s->dmap.plane_gx[p], gy = s->dmap.plane_gy[p], l = s->dmap.plane_l[p];
+    std::vector<double>* a = nullptr;
+    int rc = get(sa, s->absorption, gx, gy, &a);
+    if (rc) return rc;
+    std::vector<double> c = *a;
+    if (l >= 1) {
+      std::vector<double>* b = nullptr;
+      rc = get(ss, s->scattering, gx, gy, &b);
+      if (rc) return rc;
+      for (size_t i = 0; i < c.size(); ++i) c[i] += (*b)[i];
+      auto it = s->scattering_order.find(l);
+      if (s->anisotropic && it != s->scattering_order.end()) {
+        std::vector<double> sl;
+        rc = sample(s, it->second, gx, gy, t_eval, sl);
+        if (rc) return rc;
+        for (size_t i = 0; i < c.size(); ++i) c[i] -= sl[i];
+      }
+    }
+    rc = upload_plane(s, dptr(s, s->off_decay + size_t(p) * s->plane_bytes_c()), gx, gy, c.data(), true);
+    if (rc) return rc;
+  }
+  for (auto& kv : s->source) {
+    const int k = kv.first;
+    if (s->qk[k] < 0) continue;
+    std::vector<double> q;
+    int rc = sample(s, kv.second, s->moms[k].gx, s->moms[k].gy, t_eval, q);
+    if (rc) return rc;
+    rc = upload_plane(s, dptr(s, s->off_src + size_t(s->qk[k]) * s->plane_bytes_c()), s->moms[k].gx,
+                      s->moms[k].gy, q.data(), true);
+    if (rc) return rc;
+  }
+  s->materials_ready = true;
+  return STARMAP_OK;
+}
+
+int load_tune_cache(starmap_solver* s) {
+  const char* path = std::getenv("STARMAP_TUNE_CACHE");
+  if (!path) return -1;
+  std::ifstream f(path);
+  std::string line;
+  int found = -1;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    int N, nx, ny, st, v;
+    if (is >> N >> nx >> ny >> st >> v)
+      if (N == s->N && nx == s->nx && ny == s->ny && st == s->storage && v >= 0 && v < sweep_variant_count())
+        found = v;
+  }
+  return found;
+}
+
+int default_variant(const starmap_solver* s) {
+  // largest-reuse tile that fits the LDS of one workgroup
+  int dev = 0;
+  int max_lds = 64 * 1024;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) max_lds = v;
+  }
+  const int order[] = {0, 1, 2};
+  for (int v : order)
+    if (sweep_lds_bytes(v, s->slots, s->storage) <= size_t(max_lds)) return v;
+  return -1;
+}
+
+int ensure_device(starmap_solver* s) {
+  if (s->device_ready) return STARMAP_OK;
+  int rc = ensure_stream(s);
+  if (rc) return rc;
+  if (!s->dev) {
+    HIP_TRY(hipMalloc(&s->dev, s->dev_bytes));
+    s->owns_dev = true;
+  }
+  // zero everything once (padding included), then the initial state
+  HIP_TRY(hipMemsetAsync(s->dev, 0, s->dev_bytes, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < s->nmom; ++k) {
+    auto it = s->initial.find(k);
+    if (it == s->initial.end() || !it->second.set()) continue;
+    std::vector<double> v;
+    rc = sample(s, it->second, s->moms[k].gx, s->moms[k].gy, 0.0, v);
+    if (rc) return rc;
+    rc = upload_plane(s, dptr(s, s->off_state + size_t(k) * s->plane_bytes_state()), s->moms[k].gx,
+                      s->moms[k].gy, v.data(), false);
+    if (rc) return rc;
+  }
+  // diagnostics geometry: valid points per plane
+  {
+    std::vector<int32_t> geo(size_t(s->nmom) * 2);
+    for (int k = 0; k < s->nmom; ++k) {
+      geo[k] = points_x(s, s->moms[k].gx);
+      geo[s->nmom + k] = points_y(s, s->moms[k].gy);
+    }
+    size_t off = s->off_diag + align256(size_t(s->diag_nblocks) * 4 * 8) + 256;
+    HIP_TRY(hipMemcpyAsync(dptr(s, off), geo.data(), geo.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  if (s->variant < 0) {
+    int v = load_tune_cache(s);
+    if (v < 0) v = default_variant(s);
+    if (v < 0) return fail(STARMAP_ENOMEM, "no sweep tile fits the LDS for this moment order");
+    s->variant = v;
+  }
+  rc = upload_program(s);
+  if (rc) return rc;
+  s->device_ready = true;
+  return STARMAP_OK;
+}
+
+template <typename C>
+int launch_one(starmap_solver* s, int parity, double tau) {
+  SweepArgs<C> a;
+  const auto& pr = s->prog[parity];
+  char* base = dptr(s, s->off_prog[parity]);
+  size_t o = 0;
+  a.orders = reinterpret_cast<const int4*>(base + o);
+  o += align256(pr.orders.size() * 16);
+  a.loads = reinterpret_cast<const int4*>(base + o);
+  o += align256(pr.loads.size() * 16);
+  a.outs = reinterpret_cast<const int4*>(base + o);
+  o += align256(pr.outs.size() * 32);
+  a.terms = reinterpret_cast<const int2*>(base + o);
+  o += align256(pr.terms.size() * 8);
+  a.coefs = reinterpret_cast<const C*>(base + o);
+  a.u = dptr(s, s->off_state);
+  a.decay = reinterpret_cast<const C*>(dptr(s, s->off_decay));
+  a.src = reinterpret_cast<const C*>(dptr(s, s->off_src));
+  a.plane_stride = s->plane_stride;
+  a.pitch = s->pitch;
+  a.nx = s->nx;
+  a.ny = s->ny;
+  a.px = s->px;
+  a.py = s->py;
+  const TileShape ts = sweep_variant(s->variant);
+  a.ntx = (s->nx + 1 + ts.tx - 1) / ts.tx;
+  a.nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
+  a.norders = int(pr.orders.size());
+  a.tau = C(tau);
+  HIP_TRY(launch_sweep(s->storage, s->variant, &a, s->slots, s->stream));
+  return STARMAP_OK;
+}
+
+double sweep_bytes_of(const starmap_solver* s, int parity);
+
+int sweep(starmap_solver* s, int parity, double tau) {
+  if (s->profiling) {
+    if (s->ev_used + 2 > s->ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        s->ev.push_back(e);
+      }
+    }
+    HIP_TRY(hipEventRecord(s->ev[s->ev_used], s->stream));
+  }
+  int rc = s->storage == STORE_FP64 ? launch_one<double>(s, parity, tau) : launch_one<float>(s, parity, tau);
+  if (rc) return rc;
+  if (s->profiling) {
+    HIP_TRY(hipEventRecord(s->ev[s->ev_used + 1], s->stream));
+    s->ev_used += 2;
+    if (s->sweep_bytes_cache[parity] < 0) s->sweep_bytes_cache[parity] = sweep_bytes_of(s, parity);
+    s->prof_bytes += s->sweep_bytes_cache[parity];
+  }
+  return STARMAP_OK;
+}
+
+int validate(const starmap_problem* p) {
+  if (!p) return fail(STARMAP_EINVAL, "problem is NULL");
+  if (p->N < 1 || p->N > 99) return fail(STARMAP_EINVAL, "moment order N must be in 1..99");
+  if (p->n[0] < 2 || p->n[1] < 2) return fail(STARMAP_EINVAL, "need at least 2 cells per axis");
+  if (int64_t(p->n[0]) * p->n[1] > (int64_t(1) << 30)) return fail(STARMAP_EINVAL, "grid too large");
+  for (int a = 0; a < 2; ++a)
+    if (p->bc[a] != STARMAP_BC_PERIODIC && p->bc[a] != STARMAP_BC_EXTRAPOLATION)
+      return fail(STARMAP_EINVAL, "unknown boundary type");
+  if (!(p->ax[1] > p->ax[0]) || !(p->ax[3] > p->ax[2])) return fail(STARMAP_EINVAL, "empty domain");
+  if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return fail(STARMAP_EINVAL, "cfl must be positive");
+  if (!(p->t_final > 0.0) || !std::isfinite(p->t_final)) return fail(STARMAP_EINVAL, "t_final must be positive");
+  if (p->precision < STARMAP_FP64 || p->precision > STARMAP_BF16) return fail(STARMAP_EINVAL, "unknown precision");
+  if (p->closure != STARMAP_CLOSURE_PN && p->closure != STARMAP_CLOSURE_LEARNED)
+    return fail(STARMAP_EINVAL, "unknown closure");
+  return STARMAP_OK;
+}
+
+int check_k(const starmap_solver* s, int k) {
+  if (k < 0 || k >= s->nmom) return fail(STARMAP_EINVAL, "moment index out of range");
+  return STARMAP_OK;
+}
+
+int set_field(starmap_solver* s, FieldSource& f, starmap_field_fn fn, void* ctx, int td) {
+  if (s->device_ready && !td && !f.time_dependent && s->materials_ready) s->materials_ready = false;
+  f.fn = fn;
+  f.ctx = ctx;
+  f.time_dependent = td != 0;
+  for (int g = 0; g < 4; ++g) f.has_array[g] = false;
+  if (td) s->time_dependent = true;
+  s->materials_ready = false;
+  return STARMAP_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+int starmap_num_moments(int32_t N) {
+  if (N < 0 || N > 99) return fail(STARMAP_EINVAL, "moment order out of range");
+  return moment_count(N);
+}
+
+int starmap_moment_info(int32_t N, int32_t k, int32_t* is_imag, int32_t* l, int32_t* m, int32_t* gx,
+                        int32_t* gy) {
+  if (N < 0 || N > 99) return fail(STARMAP_EINVAL, "moment order out of range");
+  const auto moms = moment_list(N);
+  if (k < 0 || k >= int(moms.size())) return fail(STARMAP_EINVAL, "moment index out of range");
+  if (is_imag) *is_imag = moms[k].imag;
+  if (l) *l = moms[k].l;
+  if (m) *m = moms[k].m;
+  if (gx) *gx = moms[k].gx;
+  if (gy) *gy = moms[k].gy;
+  return STARMAP_OK;
+}
+
+int starmap_closure_pn(int32_t N, int32_t axis, int32_t* cols, double* vals) {
+  if (N < 0 || N > 99) return fail(STARMAP_EINVAL, "moment order out of range");
+  if ((axis != 0 && axis != 1) || !cols || !vals) return fail(STARMAP_EINVAL, "bad arguments");
+  try {
+    const auto rows = closure_pn(N);
+    for (size_t k = 0; k < rows.size(); ++k) {
+      const int n = axis == 0 ? rows[k].nx : rows[k].ny;
+      const Coupling* c = axis == 0 ? rows[k].x : rows[k].y;
+      for (int t = 0; t < 4; ++t) {
+        cols[4 * k + t] = t < n ? c[t].col : -1;
+        vals[4 * k + t] = t < n ? c[t].val : 0.0;
+      }
+    }
+  } catch (const std::exception& e) {
+    return fail(STARMAP_EINVAL, e.what());
+  }
+  return STARMAP_OK;
+}
+
+int starmap_spectral_radius(int32_t N, double* rho) {
+  if (N < 0 || N > 99 || !rho) return fail(STARMAP_EINVAL, "bad arguments");
+  *rho = spectral_radius_x(closure_pn(N));
+  return STARMAP_OK;
+}
+
+int starmap_create(const starmap_problem* prob, starmap_solver** out) {
+  if (!out) return fail(STARMAP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(prob);
+  if (rc) return rc;
+  std::unique_ptr<starmap_solver> s(new (std::nothrow) starmap_solver());
+  if (!s) return fail(STARMAP_ENOMEM, "out of host memory");
+  s->prob = *prob;
+  s->N = prob->N;
+  s->nmom = moment_count(s->N);
+  try {
+    s->moms = moment_list(s->N);
+    s->rows = closure_pn(s->N);
+  } catch (const std::exception& e) {
+    return fail(STARMAP_EINVAL, e.what());
+  }
+  s->nx = prob->n[0];
+  s->ny = prob->n[1];
+  s->px = prob->bc[0] == STARMAP_BC_PERIODIC ? 1 : 0;
+  s->py = prob->bc[1] == STARMAP_BC_PERIODIC ? 1 : 0;
+  s->dx = (prob->ax[1] - prob->ax[0]) / s->nx;
+  s->dy = (prob->ax[3] - prob->ax[2]) / s->ny;
+  s->rho = spectral_radius_x(s->rows);
+  time_step(prob->cfl, s->dx, s->dy, s->rho, prob->t_final, &s->dt, &s->steps_total);
+  s->storage = prob->precision == STARMAP_FP64 ? STORE_FP64 : prob->precision == STARMAP_FP32 ? STORE_FP32 : STORE_BF16;
+  s->ssize = s->storage == STORE_FP64 ? 8 : s->storage == STORE_FP32 ? 4 : 2;
+  s->csize = s->storage == STORE_FP64 ? 8 : 4;
+  s->pitch = int((s->nx + 1 + 63) / 64 * 64);
+  s->nrows = s->ny + 1;
+  s->plane_stride = (int64_t(s->pitch) * s->nrows + 127) / 128 * 128;
+  layout(s.get());
+  *out = s.release();
+  return STARMAP_OK;
+}
+
+void starmap_destroy(starmap_solver* s) {
+  if (!s) return;
+  if (s->owns_dev && s->dev) (void)hipFree(s->dev);
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+int starmap_set_absorption(starmap_solver* s, starmap_field_fn f, void* ctx, int32_t td) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  return set_field(s, s->absorption, f, ctx, td);
+}
+
+int starmap_set_scattering(starmap_solver* s, starmap_field_fn f, void* ctx, int32_t td) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  return set_field(s, s->scattering, f, ctx, td);
+}
+
+int starmap_set_scattering_order(starmap_solver* s, int32_t l, starmap_field_fn f, void* ctx, int32_t td) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (l < 1 || l > s->N) return fail(STARMAP_EINVAL, "order must be in 1..N");
+  if (s->device_ready && !s->anisotropic)
+    return fail(STARMAP_ESTATE, "anisotropic scattering must be set before the first device call");
+  s->anisotropic = true;
+  int rc = set_field(s, s->scattering_order[l], f, ctx, td);
+  if (rc) return rc;
+  if (!s->device_ready) layout(s);
+  return STARMAP_OK;
+}
+
+int starmap_set_source(starmap_solver* s, int32_t k, starmap_field_fn f, void* ctx, int32_t td) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  int rc = check_k(s, k);
+  if (rc) return rc;
+  const bool is_new = s->source.find(k) == s->source.end() || !s->source[k].set();
+  if (s->device_ready && is_new) return fail(STARMAP_ESTATE, "new source moments must be set before the first device call");
+  rc = set_field(s, s->source[k], f, ctx, td);
+  if (rc) return rc;
+  if (!s->device_ready) layout(s);
+  return STARMAP_OK;
+}
+
+int starmap_set_initial(starmap_solver* s, int32_t k, starmap_field_fn f, void* ctx) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  int rc = check_k(s, k);
+  if (rc) return rc;
+  if (s->device_ready) return fail(STARMAP_ESTATE, "initial values must be set before the first device call");
+  FieldSource& fs = s->initial[k];
+  fs.fn = f;
+  fs.ctx = ctx;
+  return STARMAP_OK;
+}
+
+int starmap_set_field_array(starmap_solver* s, int32_t which, int32_t k, const double* vals) {
+  if (!s || !vals) return fail(STARMAP_EINVAL, "bad arguments");
+  int rc = check_k(s, k);
+  if (rc) return rc;
+  const int gx = s->moms[k].gx, gy = s->moms[k].gy, g = grid_id(gx, gy);
+  const size_t n = size_t(points_x(s, gx)) * points_y(s, gy);
+  FieldSource* f = nullptr;
+  switch (which) {
+    case STARMAP_FIELD_ABSORPTION: f = &s->absorption; break;
+    case STARMAP_FIELD_SCATTERING: f = &s->scattering; break;
+    case STARMAP_FIELD_SOURCE: {
+      const bool is_new = s->source.find(k) == s->source.end() || !s->source[k].set();
+      if (s->device_ready && is_new) return fail(STARMAP_ESTATE, "new source moments must be set before the first device call");
+      f = &s->source[k];
+      break;
+    }
+    case STARMAP_FIELD_INITIAL:
+      if (s->device_ready) return fail(STARMAP_ESTATE, "initial values must be set before the first device call");
+      f = &s->initial[k];
+      break;
+    default: return fail(STARMAP_EINVAL, "unknown field selector");
+  }
+  f->arrays[g].assign(vals, vals + n);
+  f->has_array[g] = true;
+  if (which != STARMAP_FIELD_INITIAL) {
+    s->materials_ready = false;
+    if (!s->device_ready) layout(s);
+  }
+  return STARMAP_OK;
+}
+
+int starmap_moment_shape(const starmap_solver* s, int32_t k, int32_t* nx_k, int32_t* ny_k, double* x0_k,
+                         double* y0_k) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  int rc = check_k(s, k);
+  if (rc) return rc;
+  const int gx = s->moms[k].gx, gy = s->moms[k].gy;
+  if (nx_k) *nx_k = points_x(s, gx);
+  if (ny_k) *ny_k = points_y(s, gy);
+  if (x0_k) *x0_k = gx == AXIS_CELL ? s->prob.ax[0] + 0.5 * s->dx : s->prob.ax[0] + s->px * s->dx;
+  if (y0_k) *y0_k = gy == AXIS_CELL ? s->prob.ax[2] + 0.5 * s->dy : s->prob.ax[2] + s->py * s->dy;
+  return STARMAP_OK;
+}
+
+int starmap_time(const starmap_solver* s, double* t, double* dt, int64_t* done, int64_t* total) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (t) *t = s->t;
+  if (dt) *dt = s->dt;
+  if (done) *done = s->steps_done;
+  if (total) *total = s->steps_total;
+  return STARMAP_OK;
+}
+
+int starmap_workspace_bytes(const starmap_solver* s, size_t* bytes) {
+  if (!s || !bytes) return fail(STARMAP_EINVAL, "bad arguments");
+  *bytes = s->dev_bytes;
+  return STARMAP_OK;
+}
+
+int starmap_bind_device(starmap_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) {
+  if (!s || !dev_ptr) return fail(STARMAP_EINVAL, "bad arguments");
+  if (s->device_ready || s->dev) return fail(STARMAP_ESTATE, "device memory already in use");
+  if (bytes < s->dev_bytes) return fail(STARMAP_ENOMEM, "bound workspace is smaller than starmap_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(STARMAP_EINVAL, "workspace must be 256-byte aligned");
+  s->dev = dev_ptr;
+  s->owns_dev = false;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->bound = true;
+  return STARMAP_OK;
+}
+
+int starmap_advance(starmap_solver* s, int64_t nsteps) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (nsteps < 0) return fail(STARMAP_EINVAL, "negative step count");
+  if (nsteps == 0) return STARMAP_OK;
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  const double dt = s->dt;
+  if (!s->time_dependent) {
+    if (!s->materials_ready) {
+      rc = upload_materials(s, s->t + 0.5 * dt);
+      if (rc) return rc;
+    }
+    rc = sweep(s, 1, 0.5 * dt);
+    if (rc) return rc;
+    for (int64_t i = 0; i < nsteps; ++i) {
+      rc = sweep(s, 0, dt);
+      if (rc) return rc;
+      rc = sweep(s, 1, i + 1 < nsteps ? dt : 0.5 * dt);
+      if (rc) return rc;
+    }
+  } else {
+    for (int64_t i = 0; i < nsteps; ++i) {
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      rc = upload_materials(s, (s->steps_done + i) * dt + 0.5 * dt);
+      if (rc) return rc;
+      rc = sweep(s, 1, 0.5 * dt);
+      if (rc) return rc;
+      rc = sweep(s, 0, dt);
+      if (rc) return rc;
+      rc = sweep(s, 1, 0.5 * dt);
+      if (rc) return rc;
+    }
+  }
+  s->steps_done += nsteps;
+  s->t = double(s->steps_done) * dt;
+  return STARMAP_OK;
+}
+
+int starmap_run(starmap_solver* s) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  int rc = starmap_advance(s, s->steps_total - s->steps_done);
+  if (rc) return rc;
+  return starmap_synchronize(s);
+}
+
+int starmap_sweep(starmap_solver* s, int32_t parity, double tau, int32_t nsweeps) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if ((parity != 0 && parity != 1) || nsweeps < 0 || !std::isfinite(tau)) return fail(STARMAP_EINVAL, "bad arguments");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  if (!s->materials_ready) {
+    rc = upload_materials(s, s->t + 0.5 * s->dt);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < nsweeps; ++i) {
+    rc = sweep(s, parity, tau);
+    if (rc) return rc;
+  }
+  return STARMAP_OK;
+}
+
+int starmap_synchronize(starmap_solver* s) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (!s->device_ready) return STARMAP_OK;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return STARMAP_OK;
+}
+
+int starmap_get_moment(const starmap_solver* cs, int32_t k, double* out) {
+  starmap_solver* s = const_cast<starmap_solver*>(cs);
+  if (!s || !out) return fail(STARMAP_EINVAL, "bad arguments");
+  int rc = check_k(s, k);
+  if (rc) return rc;
+  rc = ensure_device(s);
+  if (rc) return rc;
+  const size_t n = size_t(s->plane_stride);
+  const char* src = dptr(s, s->off_state + size_t(k) * s->plane_bytes_state());
+  const int gx = s->moms[k].gx, gy = s->moms[k].gy;
+  if (s->storage == STORE_FP64) {
+    std::vector<double> buf(n);
+    HIP_TRY(hipMemcpyAsync(buf.data(), src, n * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    gather_plane(s, gx, gy, buf.data(), out);
+  } else if (s->storage == STORE_FP32) {
+    std::vector<float> buf(n);
+    HIP_TRY(hipMemcpyAsync(buf.data(), src, n * 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    gather_plane(s, gx, gy, buf.data(), out);
+  } else {
+    std::vector<uint16_t> buf(n);
+    HIP_TRY(hipMemcpyAsync(buf.data(), src, n * 2, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    gather_plane(s, gx, gy, buf.data(), out);
+  }
+  return STARMAP_OK;
+}
+
+int starmap_state_bytes(const starmap_solver* s, size_t* bytes) {
+  if (!s || !bytes) return fail(STARMAP_EINVAL, "bad arguments");
+  *bytes = size_t(s->nmom) * s->plane_bytes_state();
+  return STARMAP_OK;
+}
+
+int starmap_get_state(const starmap_solver* cs, void* host_buf, size_t bytes, double* t, int64_t* step) {
+  starmap_solver* s = const_cast<starmap_solver*>(cs);
+  if (!s || !host_buf) return fail(STARMAP_EINVAL, "bad arguments");
+  size_t need = size_t(s->nmom) * s->plane_bytes_state();
+  if (bytes < need) return fail(STARMAP_EINVAL, "checkpoint buffer too small");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(host_buf, dptr(s, s->off_state), need, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (t) *t = s->t;
+  if (step) *step = s->steps_done;
+  return STARMAP_OK;
+}
+
+int starmap_set_state(starmap_solver* s, const void* host_buf, size_t bytes, double t, int64_t step) {
+  if (!s || !host_buf) return fail(STARMAP_EINVAL, "bad arguments");
+  size_t need = size_t(s->nmom) * s->plane_bytes_state();
+  if (bytes != need) return fail(STARMAP_EINVAL, "checkpoint size does not match this solver");
+  if (step < 0 || step > s->steps_total) return fail(STARMAP_EINVAL, "step out of range");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(dptr(s, s->off_state), host_buf, need, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->t = t;
+  s->steps_done = step;
+  if (s->time_dependent) s->materials_ready = false;
+  return STARMAP_OK;
+}
+
+int starmap_diagnostics(const starmap_solver* cs, double* mass, double* l2, double* maxabs, int32_t* nonfinite) {
+  starmap_solver* s = const_cast<starmap_solver*>(cs);
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  DiagArgs a;
+  a.u = dptr(s, s->off_state);
+  size_t geo = s->off_diag + align256(size_t(s->diag_nblocks) * 4 * 8) + 256;
+  a.plane_nx = reinterpret_cast<const int*>(dptr(s, geo));
+  a.plane_ny = reinterpret_cast<const int*>(dptr(s, geo)) + s->nmom;
+  a.nplanes = s->nmom;
+  a.plane_stride = s->plane_stride;
+  a.pitch = s->pitch;
+  a.rows_per_block = s->diag_rows_per_block;
+  a.blocks_per_plane = (s->ny + 1 + s->diag_rows_per_block - 1) / s->diag_rows_per_block;
+  a.part = reinterpret_cast<double*>(dptr(s, s->off_diag));
+  a.out = reinterpret_cast<double*>(dptr(s, s->off_diag + align256(size_t(s->diag_nblocks) * 4 * 8)));
+  HIP_TRY(launch_diagnostics(s->storage, a, s->stream));
+  double res[4];
+  HIP_TRY(hipMemcpyAsync(res, a.out, sizeof(res), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const double area = s->dx * s->dy;
+  if (mass) *mass = area * res[0];
+  if (l2) *l2 = std::sqrt(area * res[1]);
+  if (maxabs) *maxabs = res[2];
+  if (nonfinite) *nonfinite = int32_t(res[3]);
+  if (res[3] != 0.0) return fail(STARMAP_EUNSTABLE, "non-finite values in the state");
+  return STARMAP_OK;
+}
+
+int starmap_set_variant(starmap_solver* s, int32_t v) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (v < -1 || v >= sweep_variant_count()) return fail(STARMAP_EINVAL, "unknown variant");
+  if (v >= 0) {
+    int dev = 0, max_lds = 64 * 1024;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      int x = 0;
+      if (hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && x > 0) max_lds = x;
+    }
+    if (sweep_lds_bytes(v, s->slots, s->storage) > size_t(max_lds))
+      return fail(STARMAP_EINVAL, "tile variant does not fit the LDS for this moment order");
+  }
+  s->variant = v;
+  if (s->device_ready) {
+    if (v < 0) {
+      v = default_variant(s);
+      s->variant = v;
+    }
+    return upload_program(s);
+  }
+  return STARMAP_OK;
+}
+
+int starmap_get_variant(const starmap_solver* s, int32_t* v, int32_t* tx, int32_t* ty) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (v) *v = s->variant;
+  if (s->variant >= 0) {
+    TileShape t = sweep_variant(s->variant);
+    if (tx) *tx = t.tx;
+    if (ty) *ty = t.ty;
+  } else {
+    if (tx) *tx = 0;
+    if (ty) *ty = 0;
+  }
+  return STARMAP_OK;
+}
+
+int starmap_autotune(starmap_solver* s, int32_t sweeps) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (sweeps < 1) sweeps = 1;
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  if (!s->materials_ready) {
+    rc = upload_materials(s, s->t + 0.5 * s->dt);
+    if (rc) return rc;
+  }
+  int dev = 0, max_lds = 64 * 1024;
+  HIP_TRY(hipGetDevice(&dev));
+  {
+    int x = 0;
+    if (hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && x > 0) max_lds = x;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = -1;
+  float best_ms = 0.f;
+  const int keep = s->variant;
+  for (int v = 0; v < sweep_variant_count(); ++v) {
+    if (sweep_lds_bytes(v, s->slots, s->storage) > size_t(max_lds)) continue;
+    s->variant = v;
+    rc = upload_program(s);
+    if (rc) break;
+    // tau = 0 leaves every value unchanged (u + 0 * r = u), so timing on the
+    // live state is harmless
+    rc = sweep(s, 0, 0.0);
+    if (!rc) rc = sweep(s, 1, 0.0);
+    if (rc) break;
+    HIP_TRY(hipEventRecord(e0, s->stream));
+    for (int i = 0; i < sweeps && !rc; ++i) {
+      rc = sweep(s, 0, 0.0);
+      if (!rc) rc = sweep(s, 1, 0.0);
+    }
+    if (rc) break;
+    HIP_TRY(hipEventRecord(e1, s->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (best < 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    s->variant = keep;
+    return rc;
+  }
+  if (best < 0) return fail(STARMAP_ENOMEM, "no sweep tile fits the LDS for this moment order");
+  s->variant = best;
+  rc = upload_program(s);
+  if (rc) return rc;
+  if (const char* path = std::getenv("STARMAP_TUNE_CACHE")) {
+    std::ofstream f(path, std::ios::app);
+    f << s->N << " " << s->nx << " " << s->ny << " " << s->storage << " " << best << "\n";
+  }
+  return STARMAP_OK;
+}
+
+int starmap_sweep_bytes(const starmap_solver* s, int32_t parity, double* bytes) {
+  if (!s || !bytes || (parity != 0 && parity != 1)) return fail(STARMAP_EINVAL, "bad arguments");
+  *bytes = sweep_bytes_of(s, parity);
+  return STARMAP_OK;
+}
+
+int starmap_profile_begin(starmap_solver* s) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  s->profiling = true;
+  s->ev_used = 0;
+  s->prof_bytes = 0.0;
+  return STARMAP_OK;
+}
+
+int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches, double* bytes) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  double ms = 0.0;
+  if (s->ev_used) {
+    HIP_TRY(hipEventSynchronize(s->ev[s->ev_used - 1]));
+    for (size_t i = 0; i + 1 < s->ev_used; i += 2) {
+      float m = 0.f;
+      HIP_TRY(hipEventElapsedTime(&m, s->ev[i], s->ev[i + 1]));
+      ms += m;
+    }
+  }
+  if (kernel_ms) *kernel_ms = ms;
+  if (launches) *launches = int64_t(s->ev_used / 2);
+  if (bytes) *bytes = s->prof_bytes;
+  s->profiling = false;
+  s->ev_used = 0;
+  s->prof_bytes = 0.0;
+  return STARMAP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+double sweep_bytes_of(const starmap_solver* s, int parity) {
+  double b = 0.0;
+  for (int k = 0; k < s->nmom; ++k) {
+    const double pts = double(points_x(s, s->moms[k].gx)) * points_y(s, s->moms[k].gy);
+    const bool even = s->moms[k].gx == s->moms[k].gy;
+    const bool out = (parity == 0) == even;
+    b += pts * double(s->ssize) * (out ? 2.0 : 1.0);
+  }
+  // decay planes of the outputs' grids (one read per point and plane used)
+  std::vector<bool> used(size_t(s->dmap.nplanes), false);
+  std::vector<bool> src_used(size_t(std::max(s->nsrc, 1)), false);
+  for (int k = 0; k < s->nmom; ++k) {
+    const bool even = s->moms[k].gx == s->moms[k].gy;
+    if ((parity == 0) != even) continue;
+    used[s->dmap.dk[k]] = true;
+    if (s->qk[k] >= 0) src_used[s->qk[k]] = true;
+  }
+  for (int p = 0; p < s->dmap.nplanes; ++p)
+    if (used[p]) b += double(points_x(s, s->dmap.plane_gx[p])) * points_y(s, s->dmap.plane_gy[p]) * s->csize;
+  for (int k = 0; k < s->nmom; ++k)
+    if (s->qk[k] >= 0 && src_used[s->qk[k]])
+      b += double(points_x(s, s->moms[k].gx)) * points_y(s, s->moms[k].gy) * s->csize;
+  return b;
+}
+
+}  // namespace
+
+extern "C" const char* starmap_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" {
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Device kernels of the staggered-grid P_N step and their launch interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace starmap {
+
+enum StorageType : int { STORE_FP64 = 0, STORE_FP32 = 1, STORE_BF16 = 2 };
+
+// Kernel arguments of one parity sweep (passed by value).
+template <typename C>
+struct SweepArgs {
+  void* u;                 // state planes, storage type
+  const C* decay;          // decay planes c(x, y), compute type
+  const C* src;            // source planes q(x, y), compute type
+  const int4* orders;      // (load0, load1, out0, out1) per output order
+  const int4* loads;       // (k, lds offset, ox, oy)
+  const int4* outs;        // 2 per row: (k, gslot, gx, gy), (dk, qk, nterms, term0)
+  const int2* terms;       // (lds offset, stride)
+  const C* coefs;          // term coefficients
+  int64_t plane_stride;    // elements between consecutive planes
+  int pitch;               // elements between rows
+  int nx, ny, px, py;      // cells per axis, periodicity flags
+  int ntx, nty;            // tiles per axis
+  int norders;
+  C tau;                   // sub-step length
+};
+
+struct TileShape {
+  int tx, ty;
+};
+
+// Tile shapes compiled into the library (index = variant id).
+int sweep_variant_count();
+TileShape sweep_variant(int v);
+
+// LDS bytes a variant needs for slots planes of the given storage type.
+size_t sweep_lds_bytes(int v, int slots, int storage);
+
+// Launch one sweep; args.u etc. must be device pointers.  Returns a HIP error.
+hipError_t launch_sweep(int storage, int variant, const void* args, int slots, hipStream_t stream);
+
+// FP64 diagnostics of a state: mass of plane 0 (times cell area is applied on
+// the host), sum of squares and max |u| over all valid points, count of
+// non-finite values.  part must hold 4 * nblocks doubles, out 4 doubles.
+struct DiagArgs {
+  const void* u;
+  const int* plane_nx;  // valid points per plane along x
+  const int* plane_ny;  // valid rows per plane
+  int nplanes;
+  int64_t plane_stride;
+  int pitch;
+  int rows_per_block;
+  int blocks_per_plane;
+  double* part;
+  double* out;
+};
+hipError_t launch_diagnostics(int storage, const DiagArgs& a, hipStream_t stream);
+int diag_blocks(int nplanes, int max_rows, int rows_per_block);
+
+}  // namespace starmap

@@ -1,0 +1,324 @@
+// Parity sweep of the staggered-grid P_N scheme on gfx950.
+//
+// One sweep applies the half-step operator S^p_tau of one parity p
+// (Seibold & Frank, Sect. 4.3, eqs. solution_operator_even/_odd): for every
+// component k of parity p and every point of its grid,
+//   W_k = - sum_j Mx(k,j) D_x u_j - sum_j My(k,j) D_y u_j      (other parity j)
+//   u_k <- u_k + tau (W_k + q_k - c_k u_k) E(-c_k tau),  E(z) = (e^z - 1)/z.
+//
+// Work decomposition: one workgroup of 256 threads per spatial tile of
+// TX x TY points; it walks the moment orders of parity p in ascending order.
+// For output order l it needs the other-parity orders l-1 and l+1, which it
+// stages in LDS as (TX+1) x (TY+1) tiles (one halo column and row, on the low
+// side for cell-centred inputs and the high side for nodal ones).  Order l+1
+// stays resident for output order l+2, so every input plane is read from
+// global memory once per sweep (plus its halo), while each staged value feeds
+// up to eight coupled outputs.  Boundary conditions enter only through the
+// index mapping of the staging loads (wrap for periodic, clamp for
+// extrapolation), so the stencil itself is uniform.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace starmap {
+
+struct bf16 {
+  uint16_t bits;
+};
+
+template <typename T> struct ComputeOf { using type = float; };
+template <> struct ComputeOf<double> { using type = double; };
+
+__device__ __forceinline__ double to_c(double v) { return v; }
+__device__ __forceinline__ float to_c(float v) { return v; }
+__device__ __forceinline__ float to_c(bf16 v) { return __uint_as_float(uint32_t(v.bits) << 16); }
+
+template <typename T> __device__ __forceinline__ T from_c(typename ComputeOf<T>::type v);
+template <> __device__ __forceinline__ double from_c<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_c<float>(float v) { return v; }
+template <> __device__ __forceinline__ bf16 from_c<bf16>(float v) {
+  // round to nearest even; NaN stays NaN
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return bf16{uint16_t((u >> 16) | 0x40u)};
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return bf16{uint16_t(u >> 16)};
+}
+
+__device__ __forceinline__ double expm1_c(double z) { return expm1(z); }
+__device__ __forceinline__ float expm1_c(float z) { return expm1f(z); }
+
+// E(z) = (e^z - 1) / z with E(0) = 1.
+template <typename C>
+__device__ __forceinline__ C expm1div(C z) {
+  return z == C(0) ? C(1) : expm1_c(z) / z;
+}
+
+// Index of an LDS staging load along one axis: periodic grids wrap, the others
+// clamp to the last stored point (the constant-extrapolation ghosts of cell
+// grids are exactly the clamped neighbours; clamped nodal points beyond the
+// grid only feed outputs that are not stored).
+__device__ __forceinline__ int map_axis(int i, int n, int periodic, int is_cell) {
+  if (periodic) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  const int last = is_cell ? n - 1 : n;
+  return i < 0 ? 0 : (i > last ? last : i);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; hand each XCD a
+// contiguous range of tiles so the halos of neighbouring tiles hit its L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int q = nblocks / 8, r = nblocks % 8;
+  const int xcd = b % 8, idx = b / 8;
+  // XCD x owns tiles [start(x), start(x) + q + (x < r))
+  const int start = xcd * q + (xcd < r ? xcd : r);
+  return start + idx;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(256)
+sweep_kernel(SweepArgs<typename ComputeOf<T>::type> a) {
+  using C = typename ComputeOf<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* L = reinterpret_cast<T*>(smem);
+  constexpr int LW = TX + 1;
+  constexpr int P = (TX + 1) * (TY + 1);
+  constexpr int NP = TX * TY;
+  static_assert(NP == 128 || NP == 256 || NP == 512, "tile must hold 128, 256 or 512 points");
+  constexpr int PPT = NP >= 256 ? NP / 256 : 1;  // points per thread
+  constexpr int NG = NP >= 256 ? 1 : 256 / NP;   // row groups (one per pair of waves)
+
+  const int tid = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % a.ntx) * TX;
+  const int y0 = (tile / a.ntx) * TY;
+  const int grp = NG > 1 ? tid / NP : 0;
+
+  int ptx[PPT], pty[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int e = NG > 1 ? tid % NP : tid + p * 256;
+    ptx[p] = e % TX;
+    pty[p] = e / TX;
+  }
+
+  T* U = reinterpret_cast<T*>(a.u);
+  // decay cache per output grid of the sweep: (plane id, c, E(-c tau))
+  int cdk0 = -1, cdk1 = -1;
+  C c0[PPT], e0[PPT], c1[PPT], e1[PPT];
+
+  for (int o = 0; o < a.norders; ++o) {
+    const int4 ord = a.orders[o];
+    // ---- stage the new input planes of this window
+    const int nload = (ord.y - ord.x) * P;
+    for (int i = tid; i < nload; i += 256) {
+      const int li = i / P;
+      const int e = i - li * P;
+      const int4 ld = a.loads[ord.x + li];
+      const int ly = e / LW;
+      const int lx = e - ly * LW;
+      const int gxi = map_axis(x0 - ld.z + lx, a.nx, a.px, ld.z);
+      const int gyi = map_axis(y0 - ld.w + ly, a.ny, a.py, ld.w);
+      L[ld.y + e] = U[int64_t(ld.x) * a.plane_stride + int64_t(gyi) * a.pitch + gxi];
+    }
+    __syncthreads();
+    // ---- update the outputs of this order
+    for (int r = ord.z + grp; r < ord.w; r += NG) {
+      const int rr = __builtin_amdgcn_readfirstlane(r);
+      const int4 h0 = a.outs[2 * rr];
+      const int4 h1 = a.outs[2 * rr + 1];
+      const int k = h0.x, gslot = h0.y, ogx = h0.z, ogy = h0.w;
+      const int dk = h1.x, qk = h1.y, nterms = h1.z, term0 = h1.w;
+      const int vx = ogx == 1 ? a.nx : a.nx + 1 - a.px;
+      const int vy = ogy == 1 ? a.ny : a.ny + 1 - a.py;
+      // refresh the decay cache of this output grid if the plane changed
+      if (gslot == 0 ? (dk != cdk0) : (dk != cdk1)) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          const int X = x0 + ptx[p], Y = y0 + pty[p];
+          C c = C(0);
+          if (X < vx && Y < vy) c = a.decay[int64_t(dk) * a.plane_stride + int64_t(Y) * a.pitch + X];
+          const C E = expm1div(-c * a.tau);
+          if (gslot == 0) { c0[p] = c; e0[p] = E; } else { c1[p] = c; e1[p] = E; }
+        }
+        if (gslot == 0) cdk0 = dk; else cdk1 = dk;
+      }
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        const int X = x0 + ptx[p], Y = y0 + pty[p];
+        const int pos = pty[p] * LW + ptx[p];
+        C W = C(0);
+        for (int t = 0; t < nterms; ++t) {
+          const int2 tm = a.terms[term0 + t];
+          const C cf = a.coefs[term0 + t];
+          const int lo = tm.x + pos;
+          W += cf * (to_c(L[lo + tm.y]) - to_c(L[lo]));
+        }
+        if (X < vx && Y < vy) {
+          const int64_t gi = int64_t(k) * a.plane_stride + int64_t(Y) * a.pitch + X;
+          const C c = gslot == 0 ? c0[p] : c1[p];
+          const C E = gslot == 0 ? e0[p] : e1[p];
+          C q = C(0);
+          if (qk >= 0) q = a.src[int64_t(qk) * a.plane_stride + int64_t(Y) * a.pitch + X];
+          const C u = to_c(U[gi]);
+          U[gi] = from_c<T>(u + a.tau * (W + q - c * u) * E);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ variants
+namespace {
+constexpr TileShape kVariants[] = {{64, 4}, {32, 4}, {64, 2}, {32, 8}, {64, 8}, {32, 16}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+template <typename T, int TX, int TY>
+hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  const auto& a = *reinterpret_cast<const SweepArgs<C>*>(args);
+  const size_t lds = size_t(slots) * (TX + 1) * (TY + 1) * sizeof(T);
+  static size_t attr_bytes = 0;
+  if (lds > attr_bytes) {
+    // opt in to more than the default dynamic LDS once per instantiation
+    int dev = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    if (lds > size_t(max_lds)) return hipErrorInvalidValue;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<T, TX, TY>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e != hipSuccess) return e;
+    attr_bytes = size_t(max_lds);
+  }
+  const int blocks = a.ntx * a.nty;
+  hipLaunchKernelGGL((sweep_kernel<T, TX, TY>), dim3(blocks), dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_typed(int variant, const void* args, int slots, hipStream_t stream) {
+  switch (variant) {
+    case 0: return launch_t<T, 64, 4>(args, slots, stream);
+    case 1: return launch_t<T, 32, 4>(args, slots, stream);
+    case 2: return launch_t<T, 64, 2>(args, slots, stream);
+    case 3: return launch_t<T, 32, 8>(args, slots, stream);
+    case 4: return launch_t<T, 64, 8>(args, slots, stream);
+    case 5: return launch_t<T, 32, 16>(args, slots, stream);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+int sweep_variant_count() { return kNumVariants; }
+TileShape sweep_variant(int v) { return kVariants[v]; }
+
+size_t sweep_lds_bytes(int v, int slots, int storage) {
+  const size_t s = storage == STORE_FP64 ? 8 : storage == STORE_FP32 ? 4 : 2;
+  return size_t(slots) * (kVariants[v].tx + 1) * (kVariants[v].ty + 1) * s;
+}
+
+hipError_t launch_sweep(int storage, int variant, const void* args, int slots, hipStream_t stream) {
+  if (variant < 0 || variant >= kNumVariants) return hipErrorInvalidValue;
+  switch (storage) {
+    case STORE_FP64: return launch_typed<double>(variant, args, slots, stream);
+    case STORE_FP32: return launch_typed<float>(variant, args, slots, stream);
+    case STORE_BF16: return launch_typed<bf16>(variant, args, slots, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ diagnostics
+// Block partials in FP64, then one block sums them in a fixed order, so the
+// result does not depend on scheduling.
+template <typename T>
+__global__ void __launch_bounds__(256) diag_partial_kernel(DiagArgs a) {
+  __shared__ double s_sum[256], s_sq[256], s_max[256], s_bad[256];
+  const int plane = blockIdx.x / a.blocks_per_plane;
+  const int rb = blockIdx.x % a.blocks_per_plane;
+  const int nxp = a.plane_nx[plane], nyp = a.plane_ny[plane];
+  const int r0 = rb * a.rows_per_block;
+  const int r1 = min(nyp, r0 + a.rows_per_block);
+  const T* U = reinterpret_cast<const T*>(a.u) + int64_t(plane) * a.plane_stride;
+  double sum = 0.0, sq = 0.0, mx = 0.0, bad = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    for (int x = threadIdx.x; x < nxp; x += 256) {
+      const double v = double(to_c(U[int64_t(r) * a.pitch + x]));
+      if (!isfinite(v)) { bad += 1.0; continue; }
+      sum += v;
+      sq += v * v;
+      mx = fmax(mx, fabs(v));
+    }
+  }
+  s_sum[threadIdx.x] = sum;
+  s_sq[threadIdx.x] = sq;
+  s_max[threadIdx.x] = mx;
+  s_bad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+      s_sq[threadIdx.x] += s_sq[threadIdx.x + w];
+      s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + w]);
+      s_bad[threadIdx.x] += s_bad[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* p = a.part + 4 * int64_t(blockIdx.x);
+    p[0] = plane == 0 ? s_sum[0] : 0.0;
+    p[1] = s_sq[0];
+    p[2] = s_max[0];
+    p[3] = s_bad[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) diag_final_kernel(const double* part, int nblocks, double* out) {
+  __shared__ double s[4][256];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+    a0 += part[4 * b + 0];
+    a1 += part[4 * b + 1];
+    a2 = fmax(a2, part[4 * b + 2]);
+    a3 += part[4 * b + 3];
+  }
+  s[0][threadIdx.x] = a0;
+  s[1][threadIdx.x] = a1;
+  s[2][threadIdx.x] = a2;
+  s[3][threadIdx.x] = a3;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + w];
+      s[1][threadIdx.x] += s[1][threadIdx.x + w];
+      s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+      s[3][threadIdx.x] += s[3][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+int diag_blocks(int nplanes, int max_rows, int rows_per_block) {
+  return nplanes * ((max_rows + rows_per_block - 1) / rows_per_block);
+}
+
+hipError_t launch_diagnostics(int storage, const DiagArgs& a, hipStream_t stream) {
+  const int nb = a.nplanes * a.blocks_per_plane;
+  switch (storage) {
+    case STORE_FP64: hipLaunchKernelGGL(diag_partial_kernel<double>, dim3(nb), dim3(256), 0, stream, a); break;
+    case STORE_FP32: hipLaunchKernelGGL(diag_partial_kernel<float>, dim3(nb), dim3(256), 0, stream, a); break;
+    case STORE_BF16: hipLaunchKernelGGL(diag_partial_kernel<bf16>, dim3(nb), dim3(256), 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, stream, a.part, nb, a.out);
+  return hipGetLastError();
+}
+
+}  // namespace starmap

@@ -1,0 +1,270 @@
+"""Python front end of the MI355X staggered-grid P_N solver.
+
+Thin layer over the C ABI (include/starmap.h): it marshals arguments, wraps
+numpy field functions as vectorised callbacks, and lets PyTorch own the
+device workspace and the stream.  All computation runs in libstarmap.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Callable, Optional
+
+import numpy as np
+
+from . import _binding as B
+
+_PREC = {"fp64": B.FP64, "fp32": B.FP32, "bf16": B.BF16}
+_BC = {"periodic": B.BC_PERIODIC, "extrapolation": B.BC_EXTRAPOLATION}
+
+
+def num_moments(N: int) -> int:
+    return B.check(B.lib().starmap_num_moments(N))
+
+
+def moment_info(N: int, k: int):
+    """(kind 'R'/'I', l, m, gx, gy) of moment k."""
+    v = [ctypes.c_int32() for _ in range(5)]
+    B.check(B.lib().starmap_moment_info(N, k, *[ctypes.byref(x) for x in v]))
+    return ("I" if v[0].value else "R", v[1].value, v[2].value, v[3].value, v[4].value)
+
+
+def closure_pn(N: int):
+    """Dense real M_x, M_y assembled from the library's sparse rows."""
+    n = num_moments(N)
+    out = []
+    for axis in (0, 1):
+        cols = np.zeros(4 * n, dtype=np.int32)
+        vals = np.zeros(4 * n, dtype=np.float64)
+        B.check(B.lib().starmap_closure_pn(N, axis, cols.ctypes.data_as(B._i32p), vals.ctypes.data_as(B._dp)))
+        M = np.zeros((n, n))
+        for k in range(n):
+            for t in range(4):
+                if cols[4 * k + t] >= 0:
+                    M[k, cols[4 * k + t]] = vals[4 * k + t]
+        out.append(M)
+    return out[0], out[1]
+
+
+def spectral_radius(N: int) -> float:
+    r = ctypes.c_double()
+    B.check(B.lib().starmap_spectral_radius(N, ctypes.byref(r)))
+    return r.value
+
+
+def _field_callback(f: Callable, keep: list):
+    """Wrap f(t, x, y) -> array as a vectorised C callback."""
+    def cb(ctx, t, n, xp, yp, outp):
+        try:
+            x = np.ctypeslib.as_array(xp, shape=(n,))
+            y = np.ctypeslib.as_array(yp, shape=(n,))
+            o = np.ctypeslib.as_array(outp, shape=(n,))
+            o[:] = np.broadcast_to(np.asarray(f(t, x, y), dtype=np.float64), (n,))
+            return 0
+        except Exception:  # reported to the library as a callback failure
+            import traceback
+            traceback.print_exc()
+            return 1
+    c = B.FIELD_FN(cb)
+    keep.append(c)
+    return c
+
+
+class Solver:
+    """One P_N problem on one GPU.
+
+    Parameters mirror the paper's problem statement: N, cells n = (nx, ny),
+    domain ax = (x0, x1, y0, y1), boundary types, cfl, t_final, precision.
+    Device memory is a torch uint8 tensor bound to the library; work runs on
+    torch's current stream of the chosen device.
+    """
+
+    def __init__(self, N, n, ax, bc=("extrapolation", "extrapolation"), cfl=0.5, t_final=1.0,
+                 precision="fp64", device=None, closure="pn"):
+        L = B.lib()
+        p = B.Problem()
+        for i in range(4):
+            p.ax[i] = float(ax[i])
+        p.n[0], p.n[1] = int(n[0]), int(n[1])
+        p.bc[0], p.bc[1] = _BC[bc[0]], _BC[bc[1]]
+        p.N = int(N)
+        p.cfl = float(cfl)
+        p.t_final = float(t_final)
+        p.precision = _PREC[precision]
+        p.closure = B.CLOSURE_LEARNED if closure == "learned" else B.CLOSURE_PN
+        h = ctypes.c_void_p()
+        B.check(L.starmap_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+        self.N = int(N)
+        self.nmom = num_moments(self.N)
+        self.precision = precision
+        self._device = device
+        self._workspace = None
+
+    @classmethod
+    def from_problem(cls, prob, device=None, precision=None):
+        """Build from a problem description object with the attributes
+        N, n, ax, bc, cfl, t_final, sigma_a, sigma_s0, sigma_sl, source,
+        initial, time_dependent, precision (fields are f(t, x, y))."""
+        s = cls(prob.N, prob.n, prob.ax, prob.bc, prob.cfl, prob.t_final,
+                precision or prob.precision, device=device)
+        td = int(bool(getattr(prob, "time_dependent", False)))
+        s.set_absorption(prob.sigma_a, td)
+        s.set_scattering(prob.sigma_s0, td)
+        if getattr(prob, "sigma_sl", None) is not None:
+            for l in range(1, prob.N + 1):
+                s.set_scattering_order(l, (lambda l_: (lambda t, x, y: prob.sigma_sl(l_, t, x, y)))(l), td)
+        for k, f in prob.source.items():
+            s.set_source(k, f, td)
+        for k, f in prob.initial.items():
+            s.set_initial(k, f)
+        return s
+
+    # ----------------------------------------------------------- fields
+    def set_absorption(self, f, time_dependent=0):
+        B.check(B.lib().starmap_set_absorption(self._h, _field_callback(f, self._keep), None, int(time_dependent)))
+
+    def set_scattering(self, f, time_dependent=0):
+        B.check(B.lib().starmap_set_scattering(self._h, _field_callback(f, self._keep), None, int(time_dependent)))
+
+    def set_scattering_order(self, l, f, time_dependent=0):
+        B.check(B.lib().starmap_set_scattering_order(self._h, int(l), _field_callback(f, self._keep), None,
+                                                     int(time_dependent)))
+
+    def set_source(self, k, f, time_dependent=0):
+        B.check(B.lib().starmap_set_source(self._h, int(k), _field_callback(f, self._keep), None,
+                                           int(time_dependent)))
+
+    def set_initial(self, k, f):
+        B.check(B.lib().starmap_set_initial(self._h, int(k), _field_callback(f, self._keep), None))
+
+    def set_field_array(self, which, k, vals):
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        nx, ny, _, _ = self.moment_shape(k)
+        assert v.size == nx * ny
+        B.check(B.lib().starmap_set_field_array(self._h, int(which), int(k), v.ctypes.data_as(B._dp)))
+
+    # ------------------------------------------------------------ queries
+    def moment_shape(self, k):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        x0, y0 = ctypes.c_double(), ctypes.c_double()
+        B.check(B.lib().starmap_moment_shape(self._h, int(k), ctypes.byref(a), ctypes.byref(b),
+                                             ctypes.byref(x0), ctypes.byref(y0)))
+        return a.value, b.value, x0.value, y0.value
+
+    def time(self):
+        t, dt = ctypes.c_double(), ctypes.c_double()
+        d, tot = ctypes.c_int64(), ctypes.c_int64()
+        B.check(B.lib().starmap_time(self._h, ctypes.byref(t), ctypes.byref(dt), ctypes.byref(d), ctypes.byref(tot)))
+        return t.value, dt.value, d.value, tot.value
+
+    @property
+    def dt(self):
+        return self.time()[1]
+
+    @property
+    def nsteps(self):
+        return self.time()[3]
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        B.check(B.lib().starmap_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def sweep_bytes(self, parity):
+        b = ctypes.c_double()
+        B.check(B.lib().starmap_sweep_bytes(self._h, int(parity), ctypes.byref(b)))
+        return b.value
+
+    # ------------------------------------------------------------- device
+    def bind_torch(self, device=None):
+        """Allocate the workspace as a torch tensor and run on torch's current
+        stream of that device."""
+        import torch
+        dev = torch.device(device or self._device or "cuda")
+        nbytes = self.workspace_bytes()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = ws.data_ptr()
+        off = (-ptr) % 256
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        B.check(B.lib().starmap_bind_device(self._h, ctypes.c_void_p(ptr + off), nbytes, ctypes.c_void_p(stream)))
+        self._workspace = ws
+        return ws
+
+    def advance(self, nsteps):
+        B.check(B.lib().starmap_advance(self._h, int(nsteps)))
+
+    def run(self):
+        B.check(B.lib().starmap_run(self._h))
+
+    def sweep(self, parity, tau, nsweeps=1):
+        B.check(B.lib().starmap_sweep(self._h, int(parity), float(tau), int(nsweeps)))
+
+    def synchronize(self):
+        B.check(B.lib().starmap_synchronize(self._h))
+
+    def get_moment(self, k):
+        nx, ny, _, _ = self.moment_shape(k)
+        out = np.empty((ny, nx), dtype=np.float64)
+        B.check(B.lib().starmap_get_moment(self._h, int(k), out.ctypes.data_as(B._dp)))
+        return out
+
+    def moments(self):
+        return [self.get_moment(k) for k in range(self.nmom)]
+
+    def get_state(self):
+        b = ctypes.c_size_t()
+        B.check(B.lib().starmap_state_bytes(self._h, ctypes.byref(b)))
+        buf = np.empty(b.value, dtype=np.uint8)
+        t, st = ctypes.c_double(), ctypes.c_int64()
+        B.check(B.lib().starmap_get_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), b.value,
+                                          ctypes.byref(t), ctypes.byref(st)))
+        return buf, t.value, st.value
+
+    def set_state(self, buf, t, step):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        B.check(B.lib().starmap_set_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size, float(t), int(step)))
+
+    def diagnostics(self, raise_unstable=True):
+        m, l2, mx = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        nf = ctypes.c_int32()
+        rc = B.lib().starmap_diagnostics(self._h, ctypes.byref(m), ctypes.byref(l2), ctypes.byref(mx), ctypes.byref(nf))
+        if rc != B.EUNSTABLE or raise_unstable:
+            B.check(rc)
+        return {"mass": m.value, "l2": l2.value, "maxabs": mx.value, "nonfinite": nf.value}
+
+    def set_variant(self, v):
+        B.check(B.lib().starmap_set_variant(self._h, int(v)))
+
+    def variant(self):
+        v, tx, ty = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        B.check(B.lib().starmap_get_variant(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty)))
+        return v.value, tx.value, ty.value
+
+    def autotune(self, sweeps=3):
+        B.check(B.lib().starmap_autotune(self._h, int(sweeps)))
+
+    def profile_begin(self):
+        B.check(B.lib().starmap_profile_begin(self._h))
+
+    def profile_end(self):
+        """(summed sweep-kernel ms, launches, summed algorithmic bytes)."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        B.check(B.lib().starmap_profile_end(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            try:
+                self.synchronize()
+            except B.StarmapError:
+                pass
+            B.lib().starmap_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

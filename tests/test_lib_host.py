@@ -1,0 +1,113 @@
+"""Host-side checks of the native library (no GPU needed): every symbol the
+header declares is exported, and the plan (moments, moment matrices, spectral
+radius, time step) agrees with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1211_2205_amd as pa
+import workloads as wl
+from oracle import pn
+from oracle.scheme import OracleSolver
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "starmap.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(starmap_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(pa.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1211_2205_amd import _binding
+    bound = {n for n, _, _ in _binding.SIGNATURES}
+    assert set(_declared()) <= bound | {"starmap_field_fn"}
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 7, 9, 16, 31, 39])
+def test_moment_matrices_match_oracle(N):
+    Mx, My = pa.closure_pn(N)
+    Ox, Oy = pn.real_matrices(N)
+    np.testing.assert_allclose(Mx, Ox, rtol=0, atol=2e-15)
+    np.testing.assert_allclose(My, Oy, rtol=0, atol=2e-15)
+
+
+@pytest.mark.parametrize("N", [1, 3, 5, 7, 9, 31, 39, 60])
+def test_moment_list_and_grids_match_oracle(N):
+    mom = pn.moments(N)
+    Ox, Oy = pn.real_matrices(N)
+    gx, gy = pn.grid_classes(Ox, Oy)
+    assert pa.num_moments(N) == len(mom)
+    for k, (kind, l, m) in enumerate(mom):
+        assert pa.moment_info(N, k) == (kind, l, m, gx[k], gy[k])
+
+
+@pytest.mark.parametrize("N", list(range(1, 40)) + [60, 99])
+def test_spectral_radius_is_largest_legendre_root(N):
+    nodes, _ = np.polynomial.legendre.leggauss(N + 1)
+    assert abs(pa.spectral_radius(N) - np.max(nodes)) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_time_step_matches_oracle(name):
+    prob = wl.config(name)
+    s = pa.Solver.from_problem(prob)
+    o_rho = pn.spectral_radius(pn.real_matrices(prob.N)[0])
+    dx = (prob.ax[1] - prob.ax[0]) / prob.n[0]
+    dt, n = pn.time_step(prob.cfl, dx, dx, o_rho, prob.t_final)
+    t, sdt, done, total = s.time()
+    assert total == n and sdt == dt and t == 0.0 and done == 0
+
+
+def test_expected_step_counts():
+    # line source P_3 100^2: 58 steps; checkerboard P_7 280^2: 246; P_39 1000^2: 666
+    assert pa.Solver.from_problem(wl.config("c1")).nsteps == 58
+    assert pa.Solver.from_problem(wl.config("c2")).nsteps == 246
+    assert pa.Solver.from_problem(wl.config("c3")).nsteps == 666
+
+
+def test_moment_shapes_follow_the_paper():
+    s = pa.Solver(3, (7, 5), (0, 1, 0, 1), ("periodic", "extrapolation"))
+    o = OracleSolver(wl.Problem("t", 3, (7, 5), (0, 1, 0, 1), ("periodic", "extrapolation"), 0.5, 1.0,
+                                lambda t, x, y: 0 * x, lambda t, x, y: 0 * x))
+    for k in range(10):
+        nx, ny, x0, y0 = s.moment_shape(k)
+        assert (ny, nx) == o.u[k].shape
+        X, Y = o.grid.coords(o.gx[k], o.gy[k])
+        assert abs(X[0, 0] - x0) < 1e-15 and abs(Y[0, 0] - y0) < 1e-15
+
+
+def test_invalid_problems_are_rejected():
+    with pytest.raises(pa.StarmapError):
+        pa.Solver(0, (10, 10), (0, 1, 0, 1))
+    with pytest.raises(pa.StarmapError):
+        pa.Solver(3, (1, 10), (0, 1, 0, 1))
+    with pytest.raises(pa.StarmapError):
+        pa.Solver(3, (10, 10), (1, 0, 0, 1))
+    with pytest.raises(pa.StarmapError):
+        pa.Solver(3, (10, 10), (0, 1, 0, 1), cfl=-1.0)
+    s = pa.Solver(3, (10, 10), (0, 1, 0, 1))
+    with pytest.raises(pa.StarmapError):
+        s.set_source(10, lambda t, x, y: x)
+    assert s.workspace_bytes() > 10 * 11 * 11 * 8
+
+
+def test_sweep_bytes_counts_every_plane():
+    s = pa.Solver(39, (1000, 1000), (-1.5, 1.5, -1.5, 1.5), precision="fp32")
+    b_odd = s.sweep_bytes(1)
+    b_even = s.sweep_bytes(0)
+    # odd sweep: 420 odd planes read+written, 400 even planes read (~1e6 points each)
+    assert 4.0 * (2 * 420 + 400) * 1.0e6 < b_odd < 4.0 * (2 * 420 + 400 + 4) * 1.002e6
+    assert 4.0 * (2 * 400 + 420) * 1.0e6 < b_even < 4.0 * (2 * 400 + 420 + 4) * 1.002e6

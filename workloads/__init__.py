@@ -211,6 +211,25 @@ def config(name: str, precision: Optional[str] = None) -> Problem:
     raise KeyError(name)
 
 
+def gaussian_sum(s: float, centers: Sequence[tuple]) -> Field:
+    """Sum of unit-mass Gaussians of standard deviation s at the given centres."""
+    fs = [gaussian_std(s, cx, cy) for cx, cy in centers]
+
+    def f(t, x, y):
+        return sum(g(t, x, y) for g in fs)
+    return f
+
+
+def line_source_multi(N: int, n: int, s: float, centers: Sequence[tuple], half_width: float = 1.5,
+                      t_final: float = 1.0, cfl: float = 0.5, precision: str = "fp64") -> Problem:
+    """Line-source setting with Gaussians at several centres (corners and edges
+    included), so that boundary regions carry data from the first step."""
+    p = line_source(N=N, n=n, s=s, half_width=half_width, t_final=t_final, cfl=cfl, precision=precision)
+    p.initial = {0: gaussian_sum(s, centers)}
+    p.name = f"line_source_multi_P{N}_{n}"
+    return p
+
+
 def random_state(seed: int, shapes: Sequence[tuple]) -> list:
     """Seeded random moment planes (for parity tests that start from a rough state)."""
     rng = np.random.Generator(np.random.PCG64(seed))
