@@ -234,17 +234,17 @@ void layout(starmap_solver* s) {
     s->prog[p] = build_sweep_program(s->N, p, 64, 4, s->dx, s->dy, s->rows, s->dmap, s->qk);
     const auto& pr = s->prog[p];
     s->prog_bytes[p] = align256(pr.orders.size() * 16) + align256(pr.loads.size() * 16) +
-                       align256(pr.outs.size() * 32) + align256(pr.terms.size() * 8) +
-                       align256(pr.coefs.size() * s->csize);
+                       align256(pr.rows.size() * 64) + align256(pr.coefs.size() * s->csize);
   }
   s->slots = s->prog[0].slots;
   size_t off = 0;
   s->off_state = off;
-  off += size_t(s->nmom) * s->plane_bytes_state();
+  // state planes, then the source planes in the storage type (the sweep
+  // stages them into LDS like any input plane)
+  off += size_t(s->nmom + s->nsrc) * s->plane_bytes_state();
+  s->off_src = s->off_state + size_t(s->nmom) * s->plane_bytes_state();
   s->off_decay = off;
   off += size_t(s->dmap.nplanes) * s->plane_bytes_c();
-  s->off_src = off;
-  off += size_t(std::max(s->nsrc, 1)) * s->plane_bytes_c();
   for (int p = 0; p < 2; ++p) {
     s->off_prog[p] = off;
     off += s->prog_bytes[p];
@@ -263,21 +263,19 @@ int upload_program(starmap_solver* s) {
     const auto& pr = s->prog[p];
     std::vector<char> buf(s->prog_bytes[p], 0);
     size_t o = 0;
-    std::vector<int32_t> ords, loads, outs, terms;
-    for (auto& x : pr.orders) { ords.insert(ords.end(), {x.load0, x.load1, x.out0, x.out1}); }
+    std::vector<int32_t> ords, loads, rws;
+    for (auto& x : pr.orders) { ords.insert(ords.end(), {x.load0, x.load1, x.row0, x.row1}); }
     for (auto& x : pr.loads) { loads.insert(loads.end(), {x.k, x.lds, x.ox, x.oy}); }
-    for (auto& x : pr.outs) {
-      outs.insert(outs.end(), {x.k, x.gslot, x.gx, x.gy, x.dk, x.qk, x.nterms, x.term0});
+    for (auto& x : pr.rows) {
+      rws.insert(rws.end(), {x.k, x.gslot, x.dk, x.so, x.xo[0], x.xo[1], x.xo[2], x.xo[3], x.yo[0], x.yo[1],
+                             x.yo[2], x.yo[3], x.nx, x.ny, 0, 0});
     }
-    for (auto& x : pr.terms) { terms.insert(terms.end(), {x.off, x.stride}); }
     std::memcpy(buf.data() + o, ords.data(), ords.size() * 4);
     o += align256(pr.orders.size() * 16);
     std::memcpy(buf.data() + o, loads.data(), loads.size() * 4);
     o += align256(pr.loads.size() * 16);
-    std::memcpy(buf.data() + o, outs.data(), outs.size() * 4);
-    o += align256(pr.outs.size() * 32);
-    std::memcpy(buf.data() + o, terms.data(), terms.size() * 4);
-    o += align256(pr.terms.size() * 8);
+    std::memcpy(buf.data() + o, rws.data(), rws.size() * 4);
+    o += align256(pr.rows.size() * 64);
     if (s->csize == 8) {
       std::memcpy(buf.data() + o, pr.coefs.data(), pr.coefs.size() * 8);
     } else {
@@ -343,8 +341,8 @@ int upload_materials(starmap_solver* s, double t_eval) {
     std::vector<double> q;
     int rc = sample(s, kv.second, s->moms[k].gx, s->moms[k].gy, t_eval, q);
     if (rc) return rc;
-    rc = upload_plane(s, dptr(s, s->off_src + size_t(s->qk[k]) * s->plane_bytes_c()), s->moms[k].gx,
-                      s->moms[k].gy, q.data(), true);
+    rc = upload_plane(s, dptr(s, s->off_src + size_t(s->qk[k]) * s->plane_bytes_state()), s->moms[k].gx,
+                      s->moms[k].gy, q.data(), false);
     if (rc) return rc;
   }
   s->materials_ready = true;
@@ -375,9 +373,9 @@ int default_variant(const starmap_solver* s) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) max_lds = v;
   }
-  const int order[] = {0, 1, 2};
-  for (int v : order)
-    if (sweep_lds_bytes(v, s->slots, s->storage) <= size_t(max_lds)) return v;
+  const int cap = sweep_cap_for(s->N);
+  for (int v = 0; v < sweep_variant_count(); ++v)
+    if (sweep_variant(v).cap == cap && sweep_lds_bytes(v, s->slots, s->storage) <= size_t(max_lds)) return v;
   return -1;
 }
 
@@ -435,14 +433,11 @@ int launch_one(starmap_solver* s, int parity, double tau) {
   o += align256(pr.orders.size() * 16);
   a.loads = reinterpret_cast<const int4*>(base + o);
   o += align256(pr.loads.size() * 16);
-  a.outs = reinterpret_cast<const int4*>(base + o);
-  o += align256(pr.outs.size() * 32);
-  a.terms = reinterpret_cast<const int2*>(base + o);
-  o += align256(pr.terms.size() * 8);
-  a.coefs = reinterpret_cast<const C*>(base + o);
+  a.rows = reinterpret_cast<const int*>(base + o);
+  o += align256(pr.rows.size() * 64);
+  a.rcoef = reinterpret_cast<const C*>(base + o);
   a.u = dptr(s, s->off_state);
   a.decay = reinterpret_cast<const C*>(dptr(s, s->off_decay));
-  a.src = reinterpret_cast<const C*>(dptr(s, s->off_src));
   a.plane_stride = s->plane_stride;
   a.pitch = s->pitch;
   a.nx = s->nx;
@@ -453,6 +448,8 @@ int launch_one(starmap_solver* s, int parity, double tau) {
   a.ntx = (s->nx + 1 + ts.tx - 1) / ts.tx;
   a.nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
   a.norders = int(pr.orders.size());
+  a.zero_off = pr.zero_off;
+  a.parity = parity;
   a.tau = C(tau);
   HIP_TRY(launch_sweep(s->storage, s->variant, &a, s->slots, s->stream));
   return STARMAP_OK;
@@ -593,6 +590,7 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out) {
   s->pitch = int((s->nx + 1 + 63) / 64 * 64);
   s->nrows = s->ny + 1;
   s->plane_stride = (int64_t(s->pitch) * s->nrows + 127) / 128 * 128;
+  if (s->plane_stride >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "grid too large for 32-bit plane offsets");
   layout(s.get());
   *out = s.release();
   return STARMAP_OK;
@@ -942,7 +940,9 @@ int starmap_autotune(starmap_solver* s, int32_t sweeps) {
   int best = -1;
   float best_ms = 0.f;
   const int keep = s->variant;
+  const int cap = sweep_cap_for(s->N);
   for (int v = 0; v < sweep_variant_count(); ++v) {
+    if (sweep_variant(v).cap != cap) continue;
     if (sweep_lds_bytes(v, s->slots, s->storage) > size_t(max_lds)) continue;
     s->variant = v;
     rc = upload_program(s);
@@ -962,6 +962,11 @@ int starmap_autotune(starmap_solver* s, int32_t sweeps) {
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (std::getenv("STARMAP_VERBOSE")) {
+      const TileShape ts = sweep_variant(v);
+      std::fprintf(stderr, "starmap autotune: variant %d (%dx%d) %.3f ms per sweep pair\n", v, ts.tx, ts.ty,
+                   ms / sweeps);
+    }
     if (best < 0 || ms < best_ms) {
       best = v;
       best_ms = ms;
@@ -1043,7 +1048,7 @@ double sweep_bytes_of(const starmap_solver* s, int parity) {
     if (used[p]) b += double(points_x(s, s->dmap.plane_gx[p])) * points_y(s, s->dmap.plane_gy[p]) * s->csize;
   for (int k = 0; k < s->nmom; ++k)
     if (s->qk[k] >= 0 && src_used[s->qk[k]])
-      b += double(points_x(s, s->moms[k].gx)) * points_y(s, s->moms[k].gy) * s->csize;
+      b += double(points_x(s, s->moms[k].gx)) * points_y(s, s->moms[k].gy) * s->ssize;
   return b;
 }
 

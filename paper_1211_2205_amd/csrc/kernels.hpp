@@ -12,29 +12,33 @@ enum StorageType : int { STORE_FP64 = 0, STORE_FP32 = 1, STORE_BF16 = 2 };
 // Kernel arguments of one parity sweep (passed by value).
 template <typename C>
 struct SweepArgs {
-  void* u;                 // state planes, storage type
+  void* u;                 // state planes, then source planes, storage type
   const C* decay;          // decay planes c(x, y), compute type
-  const C* src;            // source planes q(x, y), compute type
-  const int4* orders;      // (load0, load1, out0, out1) per output order
+  const int4* orders;      // (load0, load1, row0, row1) per output order
   const int4* loads;       // (k, lds offset, ox, oy)
-  const int4* outs;        // 2 per row: (k, gslot, gx, gy), (dk, qk, nterms, term0)
-  const int2* terms;       // (lds offset, stride)
-  const C* coefs;          // term coefficients
+  const int* rows;         // 16 ints per row: k, gslot, dk, source LDS offset, xo[4], yo[4], unused[4]
+  const C* rcoef;          // 8 coefficients per row (x couplings, then y couplings)
   int64_t plane_stride;    // elements between consecutive planes
   int pitch;               // elements between rows
   int nx, ny, px, py;      // cells per axis, periodicity flags
   int ntx, nty;            // tiles per axis
   int norders;
+  int zero_off;            // LDS element offset of the zero plane
+  int parity;              // 0: outputs on G11/G22, 1: outputs on G21/G12
   C tau;                   // sub-step length
 };
 
 struct TileShape {
   int tx, ty;
+  int cap;  // planes per staged window held in registers (moment orders up to cap - 1)
 };
 
 // Tile shapes compiled into the library (index = variant id).
 int sweep_variant_count();
 TileShape sweep_variant(int v);
+// register capacity class for moment order N: the smallest cap >= N + 1
+// among the compiled ones (the largest if none)
+int sweep_cap_for(int N);
 
 // LDS bytes a variant needs for slots planes of the given storage type.
 size_t sweep_lds_bytes(int v, int slots, int storage);

@@ -261,7 +261,18 @@ SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, d
   p.tx = tx;
   p.ty = ty;
   const int B = N + 1;
-  p.slots = 2 * B;
+  const int nmom = int(moms.size());
+  // two order buffers, one plane of zeros that the padding terms read, and the
+  // source tiles of this sweep's outputs (staged once, before the first order)
+  std::vector<int> src_slot(nmom, -1);
+  int nsrc_used = 0;
+  for (int k = 0; k < nmom; ++k) {
+    const bool even = moms[k].gx == moms[k].gy;
+    if (!qk.empty() && qk[k] >= 0 && (parity == 0) == even) src_slot[k] = 2 * B + 1 + nsrc_used++;
+  }
+  p.slots = 2 * B + 1 + nsrc_used;
+  const int zero_off = 2 * B * (tx + 1) * (ty + 1);
+  p.zero_off = zero_off;
   const int LW = tx + 1;
   const int P = (tx + 1) * (ty + 1);
   std::vector<int> pos_in_order(moms.size(), 0);
@@ -286,40 +297,53 @@ SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, d
         p.loads.push_back(ld);
       }
     }
+    if (l == parity) {
+      for (int k = 0; k < nmom; ++k) {
+        if (src_slot[k] < 0) continue;
+        // a source tile is read at the output point itself: no halo offset
+        p.loads.push_back({nmom + qk[k], src_slot[k] * (tx + 1) * (ty + 1), 0, 0});
+      }
+    }
     o.load1 = int(p.loads.size());
-    o.out0 = int(p.outs.size());
+    p.max_loads = std::max(p.max_loads, o.load1 - o.load0);
+    o.row0 = int(p.rows.size());
     for (size_t k = 0; k < moms.size(); ++k) {
       if (moms[k].l != l) continue;
       const auto& mk = moms[k];
-      SweepOut out;
-      out.k = int(k);
+      SweepRow row;
+      row.k = int(k);
       // output grids of the sweep: even -> G11 (slot 0), G22 (slot 1);
       // odd -> G21 (slot 0), G12 (slot 1)
-      out.gslot = (mk.gx == mk.gy) ? (mk.gx == AXIS_CELL ? 0 : 1) : (mk.gx == AXIS_NODE ? 0 : 1);
-      out.gx = mk.gx;
-      out.gy = mk.gy;
-      out.dk = dm.dk[k];
-      out.qk = qk.empty() ? -1 : qk[k];
-      out.term0 = int(p.terms.size());
+      row.gslot = (mk.gx == mk.gy) ? (mk.gx == AXIS_CELL ? 0 : 1) : (mk.gx == AXIS_NODE ? 0 : 1);
+      row.dk = dm.dk[k];
+      row.so = src_slot[k] >= 0 ? src_slot[k] * (tx + 1) * (ty + 1) : -1;
       const CouplingRow& r = rows[k];
+      double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int t = 0; t < 4; ++t) {
+        row.xo[t] = zero_off;
+        row.yo[t] = zero_off;
+      }
       for (int t = 0; t < r.nx; ++t) {
-        int j = r.x[t].col;
-        int oy = moms[j].gy == AXIS_CELL ? 1 : 0;
+        const int j = r.x[t].col;
+        const int oy = moms[j].gy == AXIS_CELL ? 1 : 0;
         // D_x at output (tx, ty): L[ty+oy][tx+1] - L[ty+oy][tx]
-        p.terms.push_back({lds_of(j) + oy * LW, 1});
-        p.coefs.push_back(-r.x[t].val / dx);
+        row.xo[t] = lds_of(j) + oy * LW;
+        cf[t] = -r.x[t].val / dx;
       }
       for (int t = 0; t < r.ny; ++t) {
-        int j = r.y[t].col;
-        int ox = moms[j].gx == AXIS_CELL ? 1 : 0;
+        const int j = r.y[t].col;
+        const int ox = moms[j].gx == AXIS_CELL ? 1 : 0;
         // D_y at output (tx, ty): L[ty+1][tx+ox] - L[ty][tx+ox]
-        p.terms.push_back({lds_of(j) + ox, LW});
-        p.coefs.push_back(-r.y[t].val / dy);
+        row.yo[t] = lds_of(j) + ox;
+        cf[4 + t] = -r.y[t].val / dy;
       }
-      out.nterms = r.nx + r.ny;
-      p.outs.push_back(out);
+      row.nx = r.nx;
+      row.ny = r.ny;
+      p.rows.push_back(row);
+      p.coefs.insert(p.coefs.end(), cf, cf + 8);
     }
-    o.out1 = int(p.outs.size());
+    o.row1 = int(p.rows.size());
+    p.max_rows = std::max(p.max_rows, o.row1 - o.row0);
     p.orders.push_back(o);
   }
   return p;

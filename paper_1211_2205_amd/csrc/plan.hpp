@@ -53,32 +53,34 @@ struct SweepLoad {
   int32_t lds;     // element offset of its LDS tile
   int32_t ox, oy;  // 1 if the input is cell-centred along x / y (halo on the low side)
 };
-struct SweepOut {
-  int32_t k;            // output plane
-  int32_t gslot;        // which of the sweep's two output grids (decay cache slot)
-  int32_t gx, gy;       // output grid types
-  int32_t dk;           // decay plane index
-  int32_t qk;           // source plane index or -1
-  int32_t nterms;       // <= 8
-  int32_t term0;        // first term index
-};
-struct SweepTerm {
-  int32_t off;     // LDS element offset of the lower sample (relative to the point)
-  int32_t stride;  // 1 for an x difference, TX+1 for a y difference
+// One output row of a sweep: the moment it updates and its (at most) four
+// x- and four y-couplings, padded with zero couplings that read the zero plane.
+struct SweepRow {
+  int32_t k;      // output plane (moment index)
+  int32_t gslot;  // which of the sweep's two output grids (decay cache slot)
+  int32_t dk;     // decay plane index
+  int32_t so;     // LDS element offset of the staged source tile, or -1
+  int32_t xo[4];  // LDS element offset of the lower sample of each x difference
+  int32_t yo[4];  // LDS element offset of the lower sample of each y difference
+  int32_t nx, ny; // real couplings among the four of each kind
 };
 struct SweepOrder {
-  int32_t load0, load1, out0, out1;
+  int32_t load0, load1, row0, row1;
 };
 
 struct SweepProgram {
   int parity = 0;  // outputs: 0 = even components (G11, G22), 1 = odd (G21, G12)
   int tx = 0, ty = 0;
-  int slots = 0;   // LDS planes
+  int slots = 0;     // LDS planes (the last one holds zeros)
+  int zero_off = 0;  // LDS element offset of the zero plane
+  int max_rows = 0;  // most output rows of one order
+  int max_loads = 0; // most planes staged for one order
   std::vector<SweepOrder> orders;
   std::vector<SweepLoad> loads;
-  std::vector<SweepOut> outs;
-  std::vector<SweepTerm> terms;
-  std::vector<double> coefs;  // W = sum coef * (hi - lo), coefficients pre-scaled by -1/h
+  std::vector<SweepRow> rows;
+  // eight coefficients per row: x couplings then y couplings, pre-scaled by
+  // -1/dx and -1/dy so that W = sum coef * (upper - lower sample)
+  std::vector<double> coefs;
 };
 
 struct DecayMap {
@@ -94,6 +96,8 @@ struct DecayMap {
 // per grid for all l >= 1.
 DecayMap decay_map(int N, bool anisotropic);
 
+// qk[k] >= 0 marks moment k as carrying source plane qk[k]; source planes are
+// stored after the nmom state planes (plane index nmom + qk[k]).
 SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, double dy,
                                  const std::vector<CouplingRow>& rows, const DecayMap& dm,
                                  const std::vector<int32_t>& qk);

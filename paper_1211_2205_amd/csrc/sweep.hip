@@ -78,18 +78,39 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   return start + idx;
 }
 
-template <typename T, int TX, int TY>
+// Scalars of a sweep; the pointers travel as separate __restrict__ kernel
+// arguments so the compiler may read the (uniform) program tables through the
+// scalar cache while the state is written.
+template <typename C>
+struct SweepScalars {
+  int64_t plane_stride;
+  int pitch, nx, ny, px, py, ntx, nty, norders, zero_off, parity;
+  C tau;
+};
+
+template <typename T, int TX, int TY, int CAP>
 __global__ void __launch_bounds__(256)
-sweep_kernel(SweepArgs<typename ComputeOf<T>::type> a) {
+sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
+             const int4* __restrict__ orders,
+             const int4* __restrict__ loads, const int* __restrict__ rows,
+             const typename ComputeOf<T>::type* __restrict__ rcoef,
+             const SweepScalars<typename ComputeOf<T>::type> a) {
   using C = typename ComputeOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   T* L = reinterpret_cast<T*>(smem);
   constexpr int LW = TX + 1;
   constexpr int P = (TX + 1) * (TY + 1);
   constexpr int NP = TX * TY;
-  static_assert(NP == 128 || NP == 256 || NP == 512, "tile must hold 128, 256 or 512 points");
-  constexpr int PPT = NP >= 256 ? NP / 256 : 1;  // points per thread
-  constexpr int NG = NP >= 256 ? 1 : 256 / NP;   // row groups (one per pair of waves)
+  static_assert(NP == 64 || NP == 128 || NP == 256 || NP == 512, "tile must hold 64..512 points");
+  constexpr int PPT = NP >= 256 ? NP / 256 : 1;  // output points per thread
+  constexpr int NG = NP >= 256 ? 1 : 256 / NP;   // row groups (one per NP/64 waves)
+  constexpr int EPT = (P + 255) / 256;           // staged elements per thread and plane
+  // Pipeline: while window o is computed, the planes of window o+1 (up to CAP)
+  // and the first RB output rows of order o+1 per group are loaded into
+  // registers.
+  constexpr int MAXP = CAP;
+  constexpr int RB = (CAP + NG - 1) / NG;
+  constexpr int LB = sizeof(T) >= 8 ? 8 : 16;  // planes per batch of the synchronous staging
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -97,91 +118,215 @@ sweep_kernel(SweepArgs<typename ComputeOf<T>::type> a) {
   const int y0 = (tile / a.ntx) * TY;
   const int grp = NG > 1 ? tid / NP : 0;
 
-  int ptx[PPT], pty[PPT];
+  // staging offsets of my LDS elements: offset = sbase + ox * sdx + oy * sdy
+  // (ox, oy = 1 for inputs cell-centred along x / y; uniform per plane)
+  int sbase[EPT], sdx[EPT], sdy[EPT];
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const int e = NG > 1 ? tid % NP : tid + p * 256;
-    ptx[p] = e % TX;
-    pty[p] = e / TX;
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + 256 * q;
+    const int ly = e / LW, lx = e - (e / LW) * LW;
+    const int gxn = map_axis(x0 + lx, a.nx, a.px, 0), gxc = map_axis(x0 - 1 + lx, a.nx, a.px, 1);
+    const int gyn = map_axis(y0 + ly, a.ny, a.py, 0), gyc = map_axis(y0 - 1 + ly, a.ny, a.py, 1);
+    sbase[q] = gyn * a.pitch + gxn;
+    sdx[q] = gxc - gxn;
+    sdy[q] = (gyc - gyn) * a.pitch;
   }
 
-  T* U = reinterpret_cast<T*>(a.u);
+  // my output points: LDS position, plane offset, and whether the point exists
+  // on each of the sweep's two output grids
+  int pos[PPT], goff[PPT];
+  bool val0[PPT], val1[PPT];
+  {
+    // even sweep: slot 0 = G11 (cell, cell), slot 1 = G22 (node, node);
+    // odd sweep:  slot 0 = G21 (node, cell), slot 1 = G12 (cell, node)
+    const int nxc = a.nx, nxn = a.nx + 1 - a.px, nyc = a.ny, nyn = a.ny + 1 - a.py;
+    const int vx0 = a.parity ? nxn : nxc, vy0 = a.parity ? nyc : nyc;
+    const int vx1 = a.parity ? nxc : nxn, vy1 = a.parity ? nyn : nyn;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      const int e = NG > 1 ? tid % NP : tid + p * 256;
+      const int tx = e % TX, ty = e / TX;
+      const int X = x0 + tx, Y = y0 + ty;
+      pos[p] = ty * LW + tx;
+      goff[p] = Y * a.pitch + X;
+      val0[p] = X < vx0 && Y < vy0;
+      val1[p] = X < vx1 && Y < vy1;
+    }
+  }
+
+  // synchronous staging of planes [b0, b1) of a load list into LDS
+  auto stage_sync = [&](int first, int b0, int b1) {
+    for (int bb = b0; bb < b1; bb += LB) {
+      T v[LB][EPT];
+#pragma unroll
+      for (int b = 0; b < LB; ++b) {
+        if (bb + b < b1) {
+          const int4 ld = loads[first + bb + b];
+          const T* src = U + int64_t(ld.x) * a.plane_stride;
+#pragma unroll
+          for (int q = 0; q < EPT; ++q)
+            if (tid + 256 * q < P) v[b][q] = src[sbase[q] + ld.z * sdx[q] + ld.w * sdy[q]];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < LB; ++b) {
+        if (bb + b < b1) {
+          const int dst = loads[first + bb + b].y;
+#pragma unroll
+          for (int q = 0; q < EPT; ++q)
+            if (tid + 256 * q < P) L[dst + tid + 256 * q] = v[b][q];
+        }
+      }
+    }
+  };
+
+  // current values of the output rows r0, r0 + NG, ... (RB of them, < r1)
+  auto load_rows = [&](C (&uv)[RB][PPT], int r0, int r1) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
+      if (r < r1) {
+        const int* rec = rows + 16 * r;
+        const T* up = U + int64_t(rec[0]) * a.plane_stride;
+        const bool s1 = rec[1] != 0;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(up[goff[p]]) : C(0);
+      }
+    }
+  };
+
+  // the padding couplings read this plane of zeros
+  for (int e = tid; e < P; e += 256) L[a.zero_off + e] = from_c<T>(C(0));
+  // prologue: the first window and the first rows
+  C ua[RB][PPT];
+  {
+    const int4 ord = orders[0];
+    stage_sync(ord.x, 0, ord.y - ord.x);
+    load_rows(ua, ord.z + grp, ord.w);
+  }
+  __syncthreads();
+
   // decay cache per output grid of the sweep: (plane id, c, E(-c tau))
   int cdk0 = -1, cdk1 = -1;
   C c0[PPT], e0[PPT], c1[PPT], e1[PPT];
 
   for (int o = 0; o < a.norders; ++o) {
-    const int4 ord = a.orders[o];
-    // ---- stage the new input planes of this window
-    const int nload = (ord.y - ord.x) * P;
-    for (int i = tid; i < nload; i += 256) {
-      const int li = i / P;
-      const int e = i - li * P;
-      const int4 ld = a.loads[ord.x + li];
-      const int ly = e / LW;
-      const int lx = e - ly * LW;
-      const int gxi = map_axis(x0 - ld.z + lx, a.nx, a.px, ld.z);
-      const int gyi = map_axis(y0 - ld.w + ly, a.ny, a.py, ld.w);
-      L[ld.y + e] = U[int64_t(ld.x) * a.plane_stride + int64_t(gyi) * a.pitch + gxi];
-    }
-    __syncthreads();
-    // ---- update the outputs of this order
-    for (int r = ord.z + grp; r < ord.w; r += NG) {
-      const int rr = __builtin_amdgcn_readfirstlane(r);
-      const int4 h0 = a.outs[2 * rr];
-      const int4 h1 = a.outs[2 * rr + 1];
-      const int k = h0.x, gslot = h0.y, ogx = h0.z, ogy = h0.w;
-      const int dk = h1.x, qk = h1.y, nterms = h1.z, term0 = h1.w;
-      const int vx = ogx == 1 ? a.nx : a.nx + 1 - a.px;
-      const int vy = ogy == 1 ? a.ny : a.ny + 1 - a.py;
-      // refresh the decay cache of this output grid if the plane changed
-      if (gslot == 0 ? (dk != cdk0) : (dk != cdk1)) {
+    const int4 ord = orders[o];
+    const bool has_next = o + 1 < a.norders;
+    const int4 nxt = has_next ? orders[o + 1] : make_int4(0, 0, 0, 0);
+    const int nl = nxt.y - nxt.x;
+    // 1. the next window into registers (every thread loads its own elements)
+    T stg[MAXP][EPT];
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          const int X = x0 + ptx[p], Y = y0 + pty[p];
-          C c = C(0);
-          if (X < vx && Y < vy) c = a.decay[int64_t(dk) * a.plane_stride + int64_t(Y) * a.pitch + X];
-          const C E = expm1div(-c * a.tau);
-          if (gslot == 0) { c0[p] = c; e0[p] = E; } else { c1[p] = c; e1[p] = E; }
-        }
-        if (gslot == 0) cdk0 = dk; else cdk1 = dk;
-      }
+    for (int b = 0; b < MAXP; ++b) {
+      if (b < nl) {
+        const int4 ld = loads[nxt.x + b];
+        const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        const int X = x0 + ptx[p], Y = y0 + pty[p];
-        const int pos = pty[p] * LW + ptx[p];
-        C W = C(0);
-        for (int t = 0; t < nterms; ++t) {
-          const int2 tm = a.terms[term0 + t];
-          const C cf = a.coefs[term0 + t];
-          const int lo = tm.x + pos;
-          W += cf * (to_c(L[lo + tm.y]) - to_c(L[lo]));
-        }
-        if (X < vx && Y < vy) {
-          const int64_t gi = int64_t(k) * a.plane_stride + int64_t(Y) * a.pitch + X;
-          const C c = gslot == 0 ? c0[p] : c1[p];
-          const C E = gslot == 0 ? e0[p] : e1[p];
-          C q = C(0);
-          if (qk >= 0) q = a.src[int64_t(qk) * a.plane_stride + int64_t(Y) * a.pitch + X];
-          const C u = to_c(U[gi]);
-          U[gi] = from_c<T>(u + a.tau * (W + q - c * u) * E);
-        }
+        for (int q = 0; q < EPT; ++q)
+          if (tid + 256 * q < P) stg[b][q] = src[sbase[q] + ld.z * sdx[q] + ld.w * sdy[q]];
       }
     }
+    // 2. the first output rows of the next order
+    C ub[RB][PPT];
+    if (has_next) load_rows(ub, nxt.z + grp, nxt.w);
+    // 3. update this order's rows from the current window
+    for (int r0 = ord.z + grp; r0 < ord.w; r0 += NG * RB) {
+      if (r0 != ord.z + grp) load_rows(ua, r0, ord.w);
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
+        if (r < ord.w) {
+          const int* rec = rows + 16 * r;
+          const C* cf = rcoef + 8 * r;
+          const int k = rec[0], gslot = rec[1], dk = rec[2], so = rec[3];
+          // refresh the decay cache of this output grid if the plane changed
+          if (gslot == 0 ? (dk != cdk0) : (dk != cdk1)) {
+            const C* dp = decay + int64_t(dk) * a.plane_stride;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+              const bool v = gslot ? val1[p] : val0[p];
+              const C c = v ? dp[goff[p]] : C(0);
+              const C E = expm1div(-c * a.tau);
+              if (gslot == 0) { c0[p] = c; e0[p] = E; } else { c1[p] = c; e1[p] = E; }
+            }
+            if (gslot == 0) cdk0 = dk; else cdk1 = dk;
+          }
+          T* up = U + int64_t(k) * a.plane_stride;
+#pragma unroll
+          for (int p = 0; p < PPT; ++p) {
+            C W = C(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const T* lp = L + rec[4 + t] + pos[p];
+              W += cf[t] * (to_c(lp[1]) - to_c(lp[0]));
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const T* lp = L + rec[8 + t] + pos[p];
+              W += cf[4 + t] * (to_c(lp[LW]) - to_c(lp[0]));
+            }
+            // the source, staged in LDS, joins the residual
+            if (so >= 0) W += to_c(L[so + pos[p]]);
+            if (gslot ? val1[p] : val0[p]) {
+              const C c = gslot ? c1[p] : c0[p];
+              const C E = gslot ? e1[p] : e0[p];
+              const C u = ua[i][p];
+              up[goff[p]] = from_c<T>(u + a.tau * (W - c * u) * E);
+            }
+          }
+        }
+      }
+    }
+    // 4. every read of the current window is done: install the next one
     __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXP; ++b) {
+      if (b < nl) {
+        const int dst = loads[nxt.x + b].y;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q)
+          if (tid + 256 * q < P) L[dst + tid + 256 * q] = stg[b][q];
+      }
+    }
+    if (nl > MAXP) stage_sync(nxt.x, MAXP, nl);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) ua[i][p] = ub[i][p];
   }
 }
 
 // ------------------------------------------------------------ variants
 namespace {
-constexpr TileShape kVariants[] = {{64, 4}, {32, 4}, {64, 2}, {32, 8}, {64, 8}, {32, 16}};
+constexpr TileShape kVariants[] = {
+    // large moment orders (up to 39 staged in registers)
+    {32, 4, 40}, {64, 2, 40}, {32, 2, 40},
+    // medium orders (up to 15)
+    {32, 4, 16}, {64, 4, 16}, {32, 8, 16}, {64, 2, 16},
+    // small orders (up to 7)
+    {32, 4, 8}, {64, 4, 8}, {32, 8, 8}, {64, 8, 8}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, int CAP>
 hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   const auto& a = *reinterpret_cast<const SweepArgs<C>*>(args);
   const size_t lds = size_t(slots) * (TX + 1) * (TY + 1) * sizeof(T);
+  SweepScalars<C> sc;
+  sc.plane_stride = a.plane_stride;
+  sc.pitch = a.pitch;
+  sc.nx = a.nx;
+  sc.ny = a.ny;
+  sc.px = a.px;
+  sc.py = a.py;
+  sc.ntx = a.ntx;
+  sc.nty = a.nty;
+  sc.norders = a.norders;
+  sc.zero_off = a.zero_off;
+  sc.parity = a.parity;
+  sc.tau = a.tau;
   static size_t attr_bytes = 0;
   if (lds > attr_bytes) {
     // opt in to more than the default dynamic LDS once per instantiation
@@ -190,25 +335,31 @@ hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
     if (lds > size_t(max_lds)) return hipErrorInvalidValue;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<T, TX, TY>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<T, TX, TY, CAP>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (e != hipSuccess) return e;
     attr_bytes = size_t(max_lds);
   }
   const int blocks = a.ntx * a.nty;
-  hipLaunchKernelGGL((sweep_kernel<T, TX, TY>), dim3(blocks), dim3(256), lds, stream, a);
+  hipLaunchKernelGGL((sweep_kernel<T, TX, TY, CAP>), dim3(blocks), dim3(256), lds, stream,
+                     reinterpret_cast<T*>(a.u), a.decay, a.orders, a.loads, a.rows, a.rcoef, sc);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_typed(int variant, const void* args, int slots, hipStream_t stream) {
   switch (variant) {
-    case 0: return launch_t<T, 64, 4>(args, slots, stream);
-    case 1: return launch_t<T, 32, 4>(args, slots, stream);
-    case 2: return launch_t<T, 64, 2>(args, slots, stream);
-    case 3: return launch_t<T, 32, 8>(args, slots, stream);
-    case 4: return launch_t<T, 64, 8>(args, slots, stream);
-    case 5: return launch_t<T, 32, 16>(args, slots, stream);
+    case 0: return launch_t<T, 32, 4, 40>(args, slots, stream);
+    case 1: return launch_t<T, 64, 2, 40>(args, slots, stream);
+    case 2: return launch_t<T, 32, 2, 40>(args, slots, stream);
+    case 3: return launch_t<T, 32, 4, 16>(args, slots, stream);
+    case 4: return launch_t<T, 64, 4, 16>(args, slots, stream);
+    case 5: return launch_t<T, 32, 8, 16>(args, slots, stream);
+    case 6: return launch_t<T, 64, 2, 16>(args, slots, stream);
+    case 7: return launch_t<T, 32, 4, 8>(args, slots, stream);
+    case 8: return launch_t<T, 64, 4, 8>(args, slots, stream);
+    case 9: return launch_t<T, 32, 8, 8>(args, slots, stream);
+    case 10: return launch_t<T, 64, 8, 8>(args, slots, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -216,6 +367,12 @@ hipError_t launch_typed(int variant, const void* args, int slots, hipStream_t st
 
 int sweep_variant_count() { return kNumVariants; }
 TileShape sweep_variant(int v) { return kVariants[v]; }
+
+int sweep_cap_for(int N) {
+  if (N + 1 <= 8) return 8;
+  if (N + 1 <= 16) return 16;
+  return 40;
+}
 
 size_t sweep_lds_bytes(int v, int slots, int storage) {
   const size_t s = storage == STORE_FP64 ? 8 : storage == STORE_FP32 ? 4 : 2;
