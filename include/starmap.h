@@ -115,6 +115,13 @@ int starmap_closure_pn(int32_t N, int32_t axis, int32_t* cols, double* vals);
    scales the admissible time step, Sect. 4.6 and Sect. 5.3). */
 int starmap_spectral_radius(int32_t N, double* rho);
 
+/* Self-check of the sweep programs the library builds for order N, tile
+   tile_x x tile_y and nchunks m ranges (with sources on three moments and
+   per-order decay): replays the staged LDS window and checks that every
+   coupling reads the plane the moment matrices require.  STARMAP_OK or
+   STARMAP_EINVAL with the failed check in starmap_last_error(). */
+int starmap_plan_check(int32_t N, int32_t tile_x, int32_t tile_y, int32_t nchunks);
+
 /* ------------------------------------------------------------- solver setup */
 
 /* Validate the problem, build the plan (moment matrices, grid classes, rho,

@@ -93,6 +93,8 @@ struct starmap_solver {
   bool materials_ready = false;  // decay and source planes uploaded for current time
   int variant = -1;              // -1: not chosen yet
   int slots = 0;
+  int nchunks = 1;               // m ranges per tile (workgroups per tile and sweep)
+  int chunk_width = 0;           // m indices per range (0: default)
   SweepProgram prog[2];
   bool prog_uploaded = false;
 
@@ -222,6 +224,16 @@ int upload_plane(starmap_solver* s, void* dst, int gx, int gy, const double* val
 
 char* dptr(const starmap_solver* s, size_t off) { return static_cast<char*>(s->dev) + off; }
 
+// m-range widths the autotuner tries (the compiled tiles stage up to ten
+// planes per order in registers, enough for ranges of up to eight indices)
+constexpr int kDefaultChunkWidth = 8;
+constexpr int kChunkWidths[] = {4, 6, 8};
+
+size_t program_bytes(const SweepProgram& pr, size_t csize) {
+  return align256(pr.chunks.size() * 16) + align256(pr.orders.size() * 16) + align256(pr.loads.size() * 16) +
+         align256(pr.rows.size() * 64) + align256(pr.coefs.size() * csize);
+}
+
 void layout(starmap_solver* s) {
   // decay planes and source planes
   s->dmap = decay_map(s->N, s->anisotropic);
@@ -229,14 +241,26 @@ void layout(starmap_solver* s) {
   s->nsrc = 0;
   for (auto& kv : s->source)
     if (kv.second.set()) s->qk[kv.first] = s->nsrc++;
-  // program sizes do not depend on the tile variant
-  for (int p = 0; p < 2; ++p) {
-    s->prog[p] = build_sweep_program(s->N, p, 64, 4, s->dx, s->dy, s->rows, s->dmap, s->qk);
-    const auto& pr = s->prog[p];
-    s->prog_bytes[p] = align256(pr.orders.size() * 16) + align256(pr.loads.size() * 16) +
-                       align256(pr.rows.size() * 64) + align256(pr.coefs.size() * s->csize);
+  // m ranges of a few indices keep a window within the register and LDS budget
+  // of the compiled tiles.  The width is tuned; the program region is sized
+  // for the narrowest candidate (most ranges), and program sizes do not depend
+  // on the tile.
+  if (s->chunk_width <= 0) {
+    s->chunk_width = kDefaultChunkWidth;
+    if (const char* w = std::getenv("STARMAP_CHUNK_WIDTH")) s->chunk_width = std::max(2, std::atoi(w));
   }
-  s->slots = s->prog[0].slots;
+  s->nchunks = sweep_chunk_count(s->N, s->chunk_width);
+  for (int p = 0; p < 2; ++p) {
+    s->prog_bytes[p] = 0;
+    for (int w : kChunkWidths) {
+      const SweepProgram pr =
+          build_sweep_program(s->N, p, 64, 4, s->dx, s->dy, s->rows, s->dmap, s->qk, sweep_chunk_count(s->N, w));
+      s->prog_bytes[p] = std::max(s->prog_bytes[p], program_bytes(pr, s->csize));
+    }
+    s->prog[p] = build_sweep_program(s->N, p, 64, 4, s->dx, s->dy, s->rows, s->dmap, s->qk, s->nchunks);
+    s->prog_bytes[p] = std::max(s->prog_bytes[p], program_bytes(s->prog[p], s->csize));
+  }
+  s->slots = std::max(s->prog[0].slots, s->prog[1].slots);
   size_t off = 0;
   s->off_state = off;
   // state planes, then the source planes in the storage type (the sweep
@@ -258,11 +282,19 @@ void layout(starmap_solver* s) {
 
 int upload_program(starmap_solver* s) {
   const TileShape ts = sweep_variant(s->variant);
+  s->nchunks = sweep_chunk_count(s->N, s->chunk_width);
   for (int p = 0; p < 2; ++p) {
-    s->prog[p] = build_sweep_program(s->N, p, ts.tx, ts.ty, s->dx, s->dy, s->rows, s->dmap, s->qk);
+    s->prog[p] = build_sweep_program(s->N, p, ts.tx, ts.ty, s->dx, s->dy, s->rows, s->dmap, s->qk, s->nchunks);
     const auto& pr = s->prog[p];
+    if (program_bytes(pr, s->csize) > s->prog_bytes[p]) return fail(STARMAP_ENOMEM, "sweep program region too small");
     std::vector<char> buf(s->prog_bytes[p], 0);
     size_t o = 0;
+    {
+      std::vector<int32_t> ch;
+      for (auto& x : pr.chunks) ch.insert(ch.end(), {x.order0, x.order1, 0, 0});
+      std::memcpy(buf.data() + o, ch.data(), ch.size() * 4);
+      o += align256(pr.chunks.size() * 16);
+    }
     std::vector<int32_t> ords, loads, rws;
     for (auto& x : pr.orders) { ords.insert(ords.end(), {x.load0, x.load1, x.row0, x.row1}); }
     for (auto& x : pr.loads) { loads.insert(loads.end(), {x.k, x.lds, x.ox, x.oy}); }
@@ -285,6 +317,7 @@ int upload_program(starmap_solver* s) {
     HIP_TRY(hipMemcpyAsync(dptr(s, s->off_prog[p]), buf.data(), buf.size(), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
   }
+  s->slots = std::max(s->prog[0].slots, s->prog[1].slots);
   s->prog_uploaded = true;
   return STARMAP_OK;
 }
@@ -357,10 +390,13 @@ int load_tune_cache(starmap_solver* s) {
   int found = -1;
   while (std::getline(f, line)) {
     std::istringstream is(line);
-    int N, nx, ny, st, v;
-    if (is >> N >> nx >> ny >> st >> v)
-      if (N == s->N && nx == s->nx && ny == s->ny && st == s->storage && v >= 0 && v < sweep_variant_count())
+    int N, nx, ny, st, v, w;
+    if (is >> N >> nx >> ny >> st >> v >> w)
+      if (N == s->N && nx == s->nx && ny == s->ny && st == s->storage && v >= 0 && v < sweep_variant_count() &&
+          w >= 2) {
         found = v;
+        s->chunk_width = w;
+      }
   }
   return found;
 }
@@ -373,9 +409,8 @@ int default_variant(const starmap_solver* s) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) max_lds = v;
   }
-  const int cap = sweep_cap_for(s->N);
   for (int v = 0; v < sweep_variant_count(); ++v)
-    if (sweep_variant(v).cap == cap && sweep_lds_bytes(v, s->slots, s->storage) <= size_t(max_lds)) return v;
+    if (sweep_lds_bytes(v, s->slots, s->storage) <= size_t(max_lds)) return v;
   return -1;
 }
 
@@ -429,6 +464,8 @@ int launch_one(starmap_solver* s, int parity, double tau) {
   const auto& pr = s->prog[parity];
   char* base = dptr(s, s->off_prog[parity]);
   size_t o = 0;
+  a.chunks = reinterpret_cast<const int4*>(base + o);
+  o += align256(pr.chunks.size() * 16);
   a.orders = reinterpret_cast<const int4*>(base + o);
   o += align256(pr.orders.size() * 16);
   a.loads = reinterpret_cast<const int4*>(base + o);
@@ -447,7 +484,7 @@ int launch_one(starmap_solver* s, int parity, double tau) {
   const TileShape ts = sweep_variant(s->variant);
   a.ntx = (s->nx + 1 + ts.tx - 1) / ts.tx;
   a.nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
-  a.norders = int(pr.orders.size());
+  a.nchunks = int(pr.chunks.size());
   a.zero_off = pr.zero_off;
   a.parity = parity;
   a.tau = C(tau);
@@ -547,6 +584,26 @@ int starmap_closure_pn(int32_t N, int32_t axis, int32_t* cols, double* vals) {
         cols[4 * k + t] = t < n ? c[t].col : -1;
         vals[4 * k + t] = t < n ? c[t].val : 0.0;
       }
+    }
+  } catch (const std::exception& e) {
+    return fail(STARMAP_EINVAL, e.what());
+  }
+  return STARMAP_OK;
+}
+
+int starmap_plan_check(int32_t N, int32_t tile_x, int32_t tile_y, int32_t nchunks) {
+  if (N < 1 || N > 99 || tile_x < 1 || tile_y < 1 || nchunks < 1) return fail(STARMAP_EINVAL, "bad arguments");
+  try {
+    const auto rows = closure_pn(N);
+    const DecayMap dm = decay_map(N, true);
+    std::vector<int32_t> qk(moment_count(N), -1);
+    qk[0] = 0;  // isotropic source on the zeroth moment
+    if (moment_count(N) > 3) qk[3] = 1;  // and one on an even moment of order 2
+    if (moment_count(N) > 1) qk[1] = 2;  // and one on an odd moment
+    for (int p = 0; p < 2; ++p) {
+      const SweepProgram pr = build_sweep_program(N, p, tile_x, tile_y, 0.1, 0.2, rows, dm, qk, nchunks);
+      const std::string e = validate_sweep_program(N, pr, rows, qk);
+      if (!e.empty()) return fail(STARMAP_EINVAL, "sweep program check failed: " + e);
     }
   } catch (const std::exception& e) {
     return fail(STARMAP_EINVAL, e.what());
@@ -937,54 +994,65 @@ int starmap_autotune(starmap_solver* s, int32_t sweeps) {
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  int best = -1;
+  int best = -1, best_w = s->chunk_width;
   float best_ms = 0.f;
-  const int keep = s->variant;
-  const int cap = sweep_cap_for(s->N);
-  for (int v = 0; v < sweep_variant_count(); ++v) {
-    if (sweep_variant(v).cap != cap) continue;
-    if (sweep_lds_bytes(v, s->slots, s->storage) > size_t(max_lds)) continue;
-    s->variant = v;
-    rc = upload_program(s);
+  const int keep = s->variant, keep_w = s->chunk_width;
+  std::vector<int> tried;
+  for (int w : kChunkWidths) {
     if (rc) break;
-    // tau = 0 leaves every value unchanged (u + 0 * r = u), so timing on the
-    // live state is harmless
-    rc = sweep(s, 0, 0.0);
-    if (!rc) rc = sweep(s, 1, 0.0);
-    if (rc) break;
-    HIP_TRY(hipEventRecord(e0, s->stream));
-    for (int i = 0; i < sweeps && !rc; ++i) {
+    const int nch = sweep_chunk_count(s->N, w);
+    if (std::find(tried.begin(), tried.end(), nch) != tried.end()) continue;  // same split as a narrower width
+    tried.push_back(nch);
+    s->chunk_width = w;
+    for (int v = 0; v < sweep_variant_count() && !rc; ++v) {
+      s->variant = v;
+      // slots depend on the width: build first, then check the LDS
+      rc = upload_program(s);
+      if (rc) break;
+      if (sweep_lds_bytes(v, s->slots, s->storage) > size_t(max_lds)) continue;
+      // tau = 0 leaves every value unchanged (u + 0 * r = u), so timing on the
+      // live state is harmless
       rc = sweep(s, 0, 0.0);
       if (!rc) rc = sweep(s, 1, 0.0);
-    }
-    if (rc) break;
-    HIP_TRY(hipEventRecord(e1, s->stream));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (std::getenv("STARMAP_VERBOSE")) {
-      const TileShape ts = sweep_variant(v);
-      std::fprintf(stderr, "starmap autotune: variant %d (%dx%d) %.3f ms per sweep pair\n", v, ts.tx, ts.ty,
-                   ms / sweeps);
-    }
-    if (best < 0 || ms < best_ms) {
-      best = v;
-      best_ms = ms;
+      if (rc) break;
+      HIP_TRY(hipEventRecord(e0, s->stream));
+      for (int i = 0; i < sweeps && !rc; ++i) {
+        rc = sweep(s, 0, 0.0);
+        if (!rc) rc = sweep(s, 1, 0.0);
+      }
+      if (rc) break;
+      HIP_TRY(hipEventRecord(e1, s->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (std::getenv("STARMAP_VERBOSE")) {
+        const TileShape ts = sweep_variant(v);
+        std::fprintf(stderr, "starmap autotune: width %d variant %d (%dx%d) %.3f ms per sweep pair\n", w, v, ts.tx,
+                     ts.ty, ms / sweeps);
+      }
+      if (best < 0 || ms < best_ms) {
+        best = v;
+        best_w = w;
+        best_ms = ms;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) {
     s->variant = keep;
+    s->chunk_width = keep_w;
+    (void)upload_program(s);
     return rc;
   }
   if (best < 0) return fail(STARMAP_ENOMEM, "no sweep tile fits the LDS for this moment order");
   s->variant = best;
+  s->chunk_width = best_w;
   rc = upload_program(s);
   if (rc) return rc;
   if (const char* path = std::getenv("STARMAP_TUNE_CACHE")) {
     std::ofstream f(path, std::ios::app);
-    f << s->N << " " << s->nx << " " << s->ny << " " << s->storage << " " << best << "\n";
+    f << s->N << " " << s->nx << " " << s->ny << " " << s->storage << " " << best << " " << best_w << "\n";
   }
   return STARMAP_OK;
 }

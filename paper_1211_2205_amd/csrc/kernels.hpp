@@ -14,6 +14,7 @@ template <typename C>
 struct SweepArgs {
   void* u;                 // state planes, then source planes, storage type
   const C* decay;          // decay planes c(x, y), compute type
+  const int4* chunks;      // (order0, order1, -, -) per m range
   const int4* orders;      // (load0, load1, row0, row1) per output order
   const int4* loads;       // (k, lds offset, ox, oy)
   const int* rows;         // 16 ints per row: k, gslot, dk, source LDS offset, xo[4], yo[4], unused[4]
@@ -22,7 +23,7 @@ struct SweepArgs {
   int pitch;               // elements between rows
   int nx, ny, px, py;      // cells per axis, periodicity flags
   int ntx, nty;            // tiles per axis
-  int norders;
+  int nchunks;             // workgroups per tile (m ranges)
   int zero_off;            // LDS element offset of the zero plane
   int parity;              // 0: outputs on G11/G22, 1: outputs on G21/G12
   C tau;                   // sub-step length
@@ -30,15 +31,12 @@ struct SweepArgs {
 
 struct TileShape {
   int tx, ty;
-  int cap;  // planes per staged window held in registers (moment orders up to cap - 1)
+  int cap;  // planes of one staged order and output rows per order held in registers
 };
 
 // Tile shapes compiled into the library (index = variant id).
 int sweep_variant_count();
 TileShape sweep_variant(int v);
-// register capacity class for moment order N: the smallest cap >= N + 1
-// among the compiled ones (the largest if none)
-int sweep_cap_for(int N);
 
 // LDS bytes a variant needs for slots planes of the given storage type.
 size_t sweep_lds_bytes(int v, int slots, int storage);

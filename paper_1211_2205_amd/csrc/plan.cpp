@@ -248,105 +248,238 @@ DecayMap decay_map(int N, bool anisotropic) {
   return dm;
 }
 
+int sweep_chunk_count(int N, int width) {
+  if (width < 2) width = 2;
+  int k = (N + 1 + width - 1) / width;
+  // every range must hold both parities of m so that no order inside a
+  // chunk's span is empty
+  return std::max(1, std::min(k, (N + 1) / 2));
+}
+
 SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, double dy,
                                  const std::vector<CouplingRow>& rows, const DecayMap& dm,
-                                 const std::vector<int32_t>& qk) {
-  // Outputs of order l (l of the sweep's parity) need the other-parity orders
-  // l-1 and l+1; orders are visited ascending and the staged planes of order
-  // l+1 are kept for the next output order.  Two LDS buffers of N+1 planes,
-  // selected by bit 1 of the input order, hold the window.
+                                 const std::vector<int32_t>& qk, int nchunks) {
+  // The outputs of one parity are split into nchunks ranges of the azimuthal
+  // index m.  A chunk's output (l, m) couples to the other parity at orders
+  // l -+ 1 and indices m -+ 1 only (Lemma 2), so the chunk needs the inputs
+  // with m' in [m0 - 1, m1].  Within a chunk, output orders are visited
+  // descending; the window holds the input orders l + 1 and l - 1, and the
+  // planes of l - 1 stay staged for output order l - 2.  Two LDS buffers of B
+  // planes (selected by bit 1 of the input order), a plane of zeros for the
+  // padding couplings, and the chunk's source tiles make up the LDS.
   const auto moms = moment_list(N);
+  const int nmom = int(moms.size());
   SweepProgram p;
   p.parity = parity;
   p.tx = tx;
   p.ty = ty;
-  const int B = N + 1;
-  const int nmom = int(moms.size());
-  // two order buffers, one plane of zeros that the padding terms read, and the
-  // source tiles of this sweep's outputs (staged once, before the first order)
-  std::vector<int> src_slot(nmom, -1);
-  int nsrc_used = 0;
-  for (int k = 0; k < nmom; ++k) {
-    const bool even = moms[k].gx == moms[k].gy;
-    if (!qk.empty() && qk[k] >= 0 && (parity == 0) == even) src_slot[k] = 2 * B + 1 + nsrc_used++;
-  }
-  p.slots = 2 * B + 1 + nsrc_used;
-  const int zero_off = 2 * B * (tx + 1) * (ty + 1);
-  p.zero_off = zero_off;
+  nchunks = std::max(1, std::min(nchunks, (N + 1) / 2));
+  p.nchunks = nchunks;
   const int LW = tx + 1;
   const int P = (tx + 1) * (ty + 1);
-  std::vector<int> pos_in_order(moms.size(), 0);
-  {
-    std::vector<int> cnt(N + 2, 0);
-    for (size_t k = 0; k < moms.size(); ++k) pos_in_order[k] = cnt[moms[k].l]++;
+  auto is_out = [&](int k) { return (parity == 0) == (moms[k].gx == moms[k].gy); };
+  // m ranges of equal width
+  std::vector<int> mlo(nchunks), mhi(nchunks);
+  for (int c = 0; c < nchunks; ++c) {
+    mlo[c] = (N + 1) * c / nchunks;
+    mhi[c] = (N + 1) * (c + 1) / nchunks;
   }
-  auto lds_of = [&](int k) { return (((moms[k].l >> 1) & 1) * B + pos_in_order[k]) * P; };
-  for (int l = parity; l <= N; l += 2) {
-    SweepOrder o;
-    o.load0 = int(p.loads.size());
-    for (int lin : {l - 1, l + 1}) {
-      if (lin < 0 || lin > N) continue;
-      if (lin == l - 1 && l != parity) continue;  // already staged by the previous order
-      for (size_t k = 0; k < moms.size(); ++k) {
-        if (moms[k].l != lin) continue;
-        SweepLoad ld;
-        ld.k = int(k);
-        ld.lds = lds_of(int(k));
-        ld.ox = moms[k].gx == AXIS_CELL ? 1 : 0;
-        ld.oy = moms[k].gy == AXIS_CELL ? 1 : 0;
-        p.loads.push_back(ld);
-      }
+  auto in_window = [&](int c, int k) { return moms[k].m >= mlo[c] - 1 && moms[k].m <= mhi[c]; };
+  // buffer size: most input planes of one order inside one chunk's window
+  int B = 1;
+  for (int c = 0; c < nchunks; ++c) {
+    std::vector<int> cnt(N + 2, 0);
+    for (int k = 0; k < nmom; ++k)
+      if (!is_out(k) && in_window(c, k)) B = std::max(B, ++cnt[moms[k].l]);
+  }
+  int max_src = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    int n = 0;
+    for (int k = 0; k < nmom; ++k)
+      if (is_out(k) && !qk.empty() && qk[k] >= 0 && moms[k].m >= mlo[c] && moms[k].m < mhi[c]) ++n;
+    max_src = std::max(max_src, n);
+  }
+  p.slots = 2 * B + 1 + max_src;
+  const int zero_off = 2 * B * P;
+  p.zero_off = zero_off;
+  p.buffer_planes = B;
+
+  for (int c = 0; c < nchunks; ++c) {
+    SweepChunk ch;
+    ch.order0 = int(p.orders.size());
+    // positions of the chunk's input planes within their order
+    std::vector<int> pos(nmom, -1);
+    {
+      std::vector<int> cnt(N + 2, 0);
+      for (int k = 0; k < nmom; ++k)
+        if (!is_out(k) && in_window(c, k)) pos[k] = cnt[moms[k].l]++;
     }
-    if (l == parity) {
-      for (int k = 0; k < nmom; ++k) {
-        if (src_slot[k] < 0) continue;
-        // a source tile is read at the output point itself: no halo offset
-        p.loads.push_back({nmom + qk[k], src_slot[k] * (tx + 1) * (ty + 1), 0, 0});
-      }
+    auto lds_of = [&](int k) { return (((moms[k].l >> 1) & 1) * B + pos[k]) * P; };
+    // source tiles of the chunk's rows
+    std::vector<int> src_off(nmom, -1);
+    {
+      int n = 0;
+      for (int k = 0; k < nmom; ++k)
+        if (is_out(k) && !qk.empty() && qk[k] >= 0 && moms[k].m >= mlo[c] && moms[k].m < mhi[c])
+          src_off[k] = (2 * B + 1 + n++) * P;
     }
-    o.load1 = int(p.loads.size());
-    p.max_loads = std::max(p.max_loads, o.load1 - o.load0);
-    o.row0 = int(p.rows.size());
-    for (size_t k = 0; k < moms.size(); ++k) {
-      if (moms[k].l != l) continue;
-      const auto& mk = moms[k];
-      SweepRow row;
-      row.k = int(k);
-      // output grids of the sweep: even -> G11 (slot 0), G22 (slot 1);
-      // odd -> G21 (slot 0), G12 (slot 1)
-      row.gslot = (mk.gx == mk.gy) ? (mk.gx == AXIS_CELL ? 0 : 1) : (mk.gx == AXIS_NODE ? 0 : 1);
-      row.dk = dm.dk[k];
-      row.so = src_slot[k] >= 0 ? src_slot[k] * (tx + 1) * (ty + 1) : -1;
-      const CouplingRow& r = rows[k];
-      double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int t = 0; t < 4; ++t) {
-        row.xo[t] = zero_off;
-        row.yo[t] = zero_off;
+    // Orders are visited from the top down: every chunk of a tile starts at
+    // the highest order at the same time, so the input planes that two
+    // neighbouring m ranges share are requested together (one HBM read, the
+    // second from L2).
+    bool first = true;
+    const int top = ((N - parity) % 2 == 0) ? N : N - 1;
+    for (int l = top; l >= parity; l -= 2) {
+      // output rows of this order inside the chunk
+      std::vector<int> outs;
+      for (int k = 0; k < nmom; ++k)
+        if (moms[k].l == l && is_out(k) && moms[k].m >= mlo[c] && moms[k].m < mhi[c]) outs.push_back(k);
+      if (outs.empty()) {
+        // m <= l: below the chunk's lowest order no rows exist, and with two
+        // or more m values per range no order inside the span is empty
+        if (first) throw std::runtime_error("sweep chunk without rows at the top order");
+        break;
       }
-      for (int t = 0; t < r.nx; ++t) {
-        const int j = r.x[t].col;
-        const int oy = moms[j].gy == AXIS_CELL ? 1 : 0;
-        // D_x at output (tx, ty): L[ty+oy][tx+1] - L[ty+oy][tx]
-        row.xo[t] = lds_of(j) + oy * LW;
-        cf[t] = -r.x[t].val / dx;
+      SweepOrder o;
+      o.load0 = int(p.loads.size());
+      for (int lin : {l + 1, l - 1}) {
+        if (lin < 0 || lin > N) continue;
+        if (lin == l + 1 && !first) continue;  // staged by the previous (higher) order
+        for (int k = 0; k < nmom; ++k) {
+          if (moms[k].l != lin || pos[k] < 0) continue;
+          SweepLoad ld;
+          ld.k = k;
+          ld.lds = lds_of(k);
+          ld.ox = moms[k].gx == AXIS_CELL ? 1 : 0;
+          ld.oy = moms[k].gy == AXIS_CELL ? 1 : 0;
+          p.loads.push_back(ld);
+        }
       }
-      for (int t = 0; t < r.ny; ++t) {
-        const int j = r.y[t].col;
-        const int ox = moms[j].gx == AXIS_CELL ? 1 : 0;
-        // D_y at output (tx, ty): L[ty+1][tx+ox] - L[ty][tx+ox]
-        row.yo[t] = lds_of(j) + ox;
-        cf[4 + t] = -r.y[t].val / dy;
+      if (first) {
+        for (int k = 0; k < nmom; ++k) {
+          if (src_off[k] < 0) continue;
+          // a source tile is read at the output point itself: no halo offset
+          p.loads.push_back({nmom + qk[k], src_off[k], 0, 0});
+        }
       }
-      row.nx = r.nx;
-      row.ny = r.ny;
-      p.rows.push_back(row);
-      p.coefs.insert(p.coefs.end(), cf, cf + 8);
+      first = false;
+      o.load1 = int(p.loads.size());
+      p.max_loads = std::max(p.max_loads, o.load1 - o.load0);
+      o.row0 = int(p.rows.size());
+      for (int k : outs) {
+        const auto& mk = moms[k];
+        SweepRow row;
+        row.k = k;
+        // output grids of the sweep: even -> G11 (slot 0), G22 (slot 1);
+        // odd -> G21 (slot 0), G12 (slot 1)
+        row.gslot = (mk.gx == mk.gy) ? (mk.gx == AXIS_CELL ? 0 : 1) : (mk.gx == AXIS_NODE ? 0 : 1);
+        row.dk = dm.dk[k];
+        row.so = src_off[k];
+        const CouplingRow& r = rows[k];
+        double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int32_t coupled[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        for (int t = 0; t < 4; ++t) {
+          row.xo[t] = zero_off;
+          row.yo[t] = zero_off;
+        }
+        for (int t = 0; t < r.nx; ++t) {
+          const int j = r.x[t].col;
+          if (pos[j] < 0) throw std::runtime_error("coupling outside the chunk window");
+          const int oy = moms[j].gy == AXIS_CELL ? 1 : 0;
+          // D_x at output (tx, ty): L[ty+oy][tx+1] - L[ty+oy][tx]
+          row.xo[t] = lds_of(j) + oy * LW;
+          cf[t] = -r.x[t].val / dx;
+          coupled[t] = j;
+        }
+        for (int t = 0; t < r.ny; ++t) {
+          const int j = r.y[t].col;
+          if (pos[j] < 0) throw std::runtime_error("coupling outside the chunk window");
+          const int ox = moms[j].gx == AXIS_CELL ? 1 : 0;
+          // D_y at output (tx, ty): L[ty+1][tx+ox] - L[ty][tx+ox]
+          row.yo[t] = lds_of(j) + ox;
+          cf[4 + t] = -r.y[t].val / dy;
+          coupled[4 + t] = j;
+        }
+        row.nx = r.nx;
+        row.ny = r.ny;
+        p.rows.push_back(row);
+        p.coefs.insert(p.coefs.end(), cf, cf + 8);
+        p.coupled.insert(p.coupled.end(), coupled, coupled + 8);
+      }
+      o.row1 = int(p.rows.size());
+      p.max_rows = std::max(p.max_rows, o.row1 - o.row0);
+      p.orders.push_back(o);
     }
-    o.row1 = int(p.rows.size());
-    p.max_rows = std::max(p.max_rows, o.row1 - o.row0);
-    p.orders.push_back(o);
+    ch.order1 = int(p.orders.size());
+    p.chunks.push_back(ch);
   }
   return p;
+}
+
+std::string validate_sweep_program(int N, const SweepProgram& p, const std::vector<CouplingRow>& rows,
+                                   const std::vector<int32_t>& qk) {
+  const auto moms = moment_list(N);
+  const int nmom = int(moms.size());
+  const int LW = p.tx + 1;
+  const int P = (p.tx + 1) * (p.ty + 1);
+  auto msg = [](const std::string& m) { return m; };
+  if (p.zero_off != 2 * p.buffer_planes * P) return msg("zero plane offset");
+  std::vector<int> seen(nmom, 0);
+  for (size_t c = 0; c < p.chunks.size(); ++c) {
+    std::vector<int> slot(p.slots, -1);
+    for (int o = p.chunks[c].order0; o < p.chunks[c].order1; ++o) {
+      const SweepOrder& ord = p.orders[o];
+      for (int i = ord.load0; i < ord.load1; ++i) {
+        const SweepLoad& ld = p.loads[i];
+        if (ld.lds % P || ld.lds / P >= p.slots || ld.lds == p.zero_off) return msg("load slot out of range");
+        slot[ld.lds / P] = ld.k;
+      }
+      for (int r = ord.row0; r < ord.row1; ++r) {
+        const SweepRow& row = p.rows[r];
+        const int k = row.k;
+        if (++seen[k] > 1) return msg("moment updated twice in one sweep");
+        if ((p.parity == 0) != (moms[k].gx == moms[k].gy)) return msg("row of the wrong parity");
+        for (int t = 0; t < 8; ++t) {
+          const int off = t < 4 ? row.xo[t] : row.yo[t - 4];
+          const int j = p.coupled[8 * r + t];
+          if (j < 0) {
+            if (off != p.zero_off || p.coefs[8 * r + t] != 0.0) return msg("padding coupling");
+            continue;
+          }
+          const int s = off / P, sub = off % P;
+          if (s >= p.slots || slot[s] != j) return msg("coupling reads a plane that is not staged");
+          const bool x = t < 4;
+          const int want = x ? (moms[j].gy == AXIS_CELL ? LW : 0) : (moms[j].gx == AXIS_CELL ? 1 : 0);
+          if (sub != want) return msg("coupling halo offset");
+          // the coupling is a real matrix entry of this row
+          const CouplingRow& cr = rows[k];
+          bool found = false;
+          const int n = x ? cr.nx : cr.ny;
+          for (int u = 0; u < n; ++u)
+            if ((x ? cr.x[u].col : cr.y[u].col) == j) found = true;
+          if (!found) return msg("coupling not in the moment matrix");
+        }
+        if (row.so >= 0) {
+          if (row.so % P || slot[row.so / P] != nmom + qk[k]) return msg("source tile not staged");
+        } else if (!qk.empty() && qk[k] >= 0) {
+          return msg("source of a row dropped");
+        }
+      }
+    }
+  }
+  for (int k = 0; k < nmom; ++k) {
+    const bool out = (p.parity == 0) == (moms[k].gx == moms[k].gy);
+    if (out && seen[k] != 1) return msg("moment not updated by its sweep");
+    // every real coupling of an updated row is present
+    if (out) {
+      int cnt = 0;
+      for (size_t r = 0; r < p.rows.size(); ++r)
+        if (p.rows[r].k == k)
+          for (int t = 0; t < 8; ++t) cnt += p.coupled[8 * r + t] >= 0;
+      if (cnt != rows[k].nx + rows[k].ny) return msg("coupling dropped");
+    }
+  }
+  return std::string();
 }
 
 }  // namespace starmap

@@ -68,11 +68,18 @@ struct SweepOrder {
   int32_t load0, load1, row0, row1;
 };
 
+struct SweepChunk {
+  int32_t order0, order1;  // output orders of one m range
+};
+
 struct SweepProgram {
   int parity = 0;  // outputs: 0 = even components (G11, G22), 1 = odd (G21, G12)
   int tx = 0, ty = 0;
-  int slots = 0;     // LDS planes (the last one holds zeros)
-  int zero_off = 0;  // LDS element offset of the zero plane
+  int nchunks = 1;       // m ranges; each tile is processed by nchunks workgroups
+  int buffer_planes = 0; // planes per order buffer
+  int slots = 0;         // LDS planes: two order buffers, the zero plane, source tiles
+  int zero_off = 0;      // LDS element offset of the zero plane
+  std::vector<SweepChunk> chunks;
   int max_rows = 0;  // most output rows of one order
   int max_loads = 0; // most planes staged for one order
   std::vector<SweepOrder> orders;
@@ -81,7 +88,15 @@ struct SweepProgram {
   // eight coefficients per row: x couplings then y couplings, pre-scaled by
   // -1/dx and -1/dy so that W = sum coef * (upper - lower sample)
   std::vector<double> coefs;
+  // host-side record of the input plane behind each coupling (-1 for padding),
+  // eight per row, for validate_sweep_program
+  std::vector<int32_t> coupled;
 };
+
+// Replays a program's LDS slot contents and checks that every coupling and
+// source read finds the plane it expects; returns an empty string or a message.
+std::string validate_sweep_program(int N, const SweepProgram& p, const std::vector<CouplingRow>& rows,
+                                   const std::vector<int32_t>& qk);
 
 struct DecayMap {
   std::vector<int32_t> dk;  // per moment: decay plane index
@@ -96,10 +111,13 @@ struct DecayMap {
 // per grid for all l >= 1.
 DecayMap decay_map(int N, bool anisotropic);
 
+// Number of m ranges of the given width for order N.
+int sweep_chunk_count(int N, int width);
+
 // qk[k] >= 0 marks moment k as carrying source plane qk[k]; source planes are
 // stored after the nmom state planes (plane index nmom + qk[k]).
 SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, double dy,
                                  const std::vector<CouplingRow>& rows, const DecayMap& dm,
-                                 const std::vector<int32_t>& qk);
+                                 const std::vector<int32_t>& qk, int nchunks);
 
 }  // namespace starmap

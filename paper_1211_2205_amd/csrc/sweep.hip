@@ -6,16 +6,18 @@
 //   W_k = - sum_j Mx(k,j) D_x u_j - sum_j My(k,j) D_y u_j      (other parity j)
 //   u_k <- u_k + tau (W_k + q_k - c_k u_k) E(-c_k tau),  E(z) = (e^z - 1)/z.
 //
-// Work decomposition: one workgroup of 256 threads per spatial tile of
-// TX x TY points; it walks the moment orders of parity p in ascending order.
-// For output order l it needs the other-parity orders l-1 and l+1, which it
-// stages in LDS as (TX+1) x (TY+1) tiles (one halo column and row, on the low
-// side for cell-centred inputs and the high side for nodal ones).  Order l+1
-// stays resident for output order l+2, so every input plane is read from
-// global memory once per sweep (plus its halo), while each staged value feeds
-// up to eight coupled outputs.  Boundary conditions enter only through the
-// index mapping of the staging loads (wrap for periodic, clamp for
-// extrapolation), so the stencil itself is uniform.
+// Work decomposition: the outputs of a sweep are split into ranges of the
+// azimuthal index m (an output (l, m) couples only to inputs (l -+ 1, m -+ 1),
+// Lemma 2).  One workgroup of 256 threads handles one spatial tile of TX x TY
+// points and one m range, walking the output orders from the top down.  For
+// output order l it needs the input orders l + 1 and l - 1 inside the m range,
+// staged in LDS as (TX+1) x (TY+1) tiles (one halo column and row, on the low
+// side for cell-centred inputs and the high side for nodal ones); order l - 1
+// stays staged for output order l - 2, and while one order is computed the
+// next order's planes and output rows are already loading into registers.
+// Every staged value feeds up to eight coupled outputs.  Boundary conditions
+// enter only through the index mapping of the staging loads (wrap for
+// periodic, clamp for extrapolation), so the stencil itself is uniform.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -84,14 +86,14 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 template <typename C>
 struct SweepScalars {
   int64_t plane_stride;
-  int pitch, nx, ny, px, py, ntx, nty, norders, zero_off, parity;
+  int pitch, nx, ny, px, py, ntx, nty, nchunks, zero_off, parity;
   C tau;
 };
 
 template <typename T, int TX, int TY, int CAP>
 __global__ void __launch_bounds__(256)
 sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
-             const int4* __restrict__ orders,
+             const int4* __restrict__ chunks, const int4* __restrict__ orders,
              const int4* __restrict__ loads, const int* __restrict__ rows,
              const typename ComputeOf<T>::type* __restrict__ rcoef,
              const SweepScalars<typename ComputeOf<T>::type> a) {
@@ -101,35 +103,76 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
   constexpr int LW = TX + 1;
   constexpr int P = (TX + 1) * (TY + 1);
   constexpr int NP = TX * TY;
-  static_assert(NP == 64 || NP == 128 || NP == 256 || NP == 512, "tile must hold 64..512 points");
-  constexpr int PPT = NP >= 256 ? NP / 256 : 1;  // output points per thread
-  constexpr int NG = NP >= 256 ? 1 : 256 / NP;   // row groups (one per NP/64 waves)
-  constexpr int EPT = (P + 255) / 256;           // staged elements per thread and plane
+  static_assert(NP == 256 || NP == 512, "tile must hold 256 or 512 points");
+  static_assert(TX + TY <= 256, "halo points must fit one per thread");
+  constexpr int PPT = NP / 256;  // output points per thread
+  constexpr int NG = 1;          // every thread owns its own points
   // Pipeline: while window o is computed, the planes of window o+1 (up to CAP)
-  // and the first RB output rows of order o+1 per group are loaded into
-  // registers.
+  // and the first RB output rows of order o+1 are loaded into registers.
   constexpr int MAXP = CAP;
-  constexpr int RB = (CAP + NG - 1) / NG;
+  constexpr int RB = CAP - 2;  // an m range of width w has w rows and w + 2 staged planes per order
   constexpr int LB = sizeof(T) >= 8 ? 8 : 16;  // planes per batch of the synchronous staging
+  constexpr int EPT = PPT + 1;                 // staged points per thread and plane: interior + halo
 
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  // logical block = tile * nchunks + chunk: the m ranges of one tile run on
+  // the same XCD, one after another, and share its L2
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = lb / a.nchunks;
+  const int4 chk = chunks[lb - tile * a.nchunks];
+  if (chk.x >= chk.y) return;  // no output rows in this m range
   const int x0 = (tile % a.ntx) * TX;
   const int y0 = (tile / a.ntx) * TY;
-  const int grp = NG > 1 ? tid / NP : 0;
+  const int grp = 0;
 
-  // staging offsets of my LDS elements: offset = sbase + ox * sdx + oy * sdy
-  // (ox, oy = 1 for inputs cell-centred along x / y; uniform per plane)
-  int sbase[EPT], sdx[EPT], sdy[EPT];
+  // Staging of one input plane into its (TX+1) x (TY+1) LDS tile.  The tile
+  // holds global points (x0 - ox + lx, y0 - oy + ly), with ox (oy) = 1 for an
+  // input cell-centred along x (y).  Thread t loads the interior point of its
+  // own output position (a wave reads whole aligned row segments) and, for
+  // t < TY + TX, one halo point: of the halo column read by x differences
+  // (lx = 0 or TX) or of the halo row read by y differences (ly = 0 or TY);
+  // the corners are never read.  Source and LDS offsets are affine in (ox, oy):
+  // src = sb + ox * sx + oy * sy, dst = db + ox * ddx + oy * ddy.
+  int sb[EPT], sx[EPT], sy[EPT], db[EPT], ddx[EPT], ddy[EPT];
+  bool sv[EPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = tid + 256 * q;
-    const int ly = e / LW, lx = e - (e / LW) * LW;
-    const int gxn = map_axis(x0 + lx, a.nx, a.px, 0), gxc = map_axis(x0 - 1 + lx, a.nx, a.px, 1);
-    const int gyn = map_axis(y0 + ly, a.ny, a.py, 0), gyc = map_axis(y0 - 1 + ly, a.ny, a.py, 1);
-    sbase[q] = gyn * a.pitch + gxn;
-    sdx[q] = gxc - gxn;
-    sdy[q] = (gyc - gyn) * a.pitch;
+  for (int p = 0; p < PPT; ++p) {
+    const int e = tid + p * 256;
+    const int tx = e % TX, ty = e / TX;
+    const int xn = map_axis(x0 + tx, a.nx, a.px, 0), xc = map_axis(x0 + tx, a.nx, a.px, 1);
+    const int yn = map_axis(y0 + ty, a.ny, a.py, 0), yc = map_axis(y0 + ty, a.ny, a.py, 1);
+    sb[p] = yn * a.pitch + xn;
+    sx[p] = xc - xn;
+    sy[p] = (yc - yn) * a.pitch;
+    db[p] = ty * LW + tx;
+    ddx[p] = 1;
+    ddy[p] = LW;
+    sv[p] = true;
+  }
+  {
+    constexpr int h = PPT;
+    sv[h] = tid < TY + TX;
+    if (tid < TY) {  // halo column, row i
+      const int i = tid;
+      const int xn = map_axis(x0 + TX, a.nx, a.px, 0), xc = map_axis(x0 - 1, a.nx, a.px, 1);
+      const int yn = map_axis(y0 + i, a.ny, a.py, 0), yc = map_axis(y0 + i, a.ny, a.py, 1);
+      sb[h] = yn * a.pitch + xn;
+      sx[h] = xc - xn;
+      sy[h] = (yc - yn) * a.pitch;
+      db[h] = i * LW + TX;
+      ddx[h] = -TX;
+      ddy[h] = LW;
+    } else {  // halo row, column j (lanes past the halo keep in-bounds values)
+      const int j = tid < TY + TX ? tid - TY : 0;
+      const int xn = map_axis(x0 + j, a.nx, a.px, 0), xc = map_axis(x0 + j, a.nx, a.px, 1);
+      const int yn = map_axis(y0 + TY, a.ny, a.py, 0), yc = map_axis(y0 - 1, a.ny, a.py, 1);
+      sb[h] = yn * a.pitch + xn;
+      sx[h] = xc - xn;
+      sy[h] = (yc - yn) * a.pitch;
+      db[h] = TY * LW + j;
+      ddx[h] = 1;
+      ddy[h] = -TY * LW;
+    }
   }
 
   // my output points: LDS position, plane offset, and whether the point exists
@@ -144,7 +187,7 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
     const int vx1 = a.parity ? nxc : nxn, vy1 = a.parity ? nyn : nyn;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      const int e = NG > 1 ? tid % NP : tid + p * 256;
+      const int e = tid + p * 256;
       const int tx = e % TX, ty = e / TX;
       const int X = x0 + tx, Y = y0 + ty;
       pos[p] = ty * LW + tx;
@@ -165,16 +208,16 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
           const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
-            if (tid + 256 * q < P) v[b][q] = src[sbase[q] + ld.z * sdx[q] + ld.w * sdy[q]];
+            if (sv[q]) v[b][q] = src[sb[q] + ld.z * sx[q] + ld.w * sy[q]];
         }
       }
 #pragma unroll
       for (int b = 0; b < LB; ++b) {
         if (bb + b < b1) {
-          const int dst = loads[first + bb + b].y;
+          const int4 ld = loads[first + bb + b];
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
-            if (tid + 256 * q < P) L[dst + tid + 256 * q] = v[b][q];
+            if (sv[q]) L[ld.y + db[q] + ld.z * ddx[q] + ld.w * ddy[q]] = v[b][q];
         }
       }
     }
@@ -200,7 +243,7 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
   // prologue: the first window and the first rows
   C ua[RB][PPT];
   {
-    const int4 ord = orders[0];
+    const int4 ord = orders[chk.x];
     stage_sync(ord.x, 0, ord.y - ord.x);
     load_rows(ua, ord.z + grp, ord.w);
   }
@@ -210,9 +253,9 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
   int cdk0 = -1, cdk1 = -1;
   C c0[PPT], e0[PPT], c1[PPT], e1[PPT];
 
-  for (int o = 0; o < a.norders; ++o) {
+  for (int o = chk.x; o < chk.y; ++o) {
     const int4 ord = orders[o];
-    const bool has_next = o + 1 < a.norders;
+    const bool has_next = o + 1 < chk.y;
     const int4 nxt = has_next ? orders[o + 1] : make_int4(0, 0, 0, 0);
     const int nl = nxt.y - nxt.x;
     // 1. the next window into registers (every thread loads its own elements)
@@ -224,7 +267,7 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
         const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
-          if (tid + 256 * q < P) stg[b][q] = src[sbase[q] + ld.z * sdx[q] + ld.w * sdy[q]];
+          if (sv[q]) stg[b][q] = src[sb[q] + ld.z * sx[q] + ld.w * sy[q]];
       }
     }
     // 2. the first output rows of the next order
@@ -240,7 +283,7 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
           const int* rec = rows + 16 * r;
           const C* cf = rcoef + 8 * r;
           const int k = rec[0], gslot = rec[1], dk = rec[2], so = rec[3];
-          // refresh the decay cache of this output grid if the plane changed
+    // refresh the decay cache of this output grid if the plane changed
           if (gslot == 0 ? (dk != cdk0) : (dk != cdk1)) {
             const C* dp = decay + int64_t(dk) * a.plane_stride;
 #pragma unroll
@@ -266,7 +309,7 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
               const T* lp = L + rec[8 + t] + pos[p];
               W += cf[4 + t] * (to_c(lp[LW]) - to_c(lp[0]));
             }
-            // the source, staged in LDS, joins the residual
+    // the source, staged in LDS, joins the residual
             if (so >= 0) W += to_c(L[so + pos[p]]);
             if (gslot ? val1[p] : val0[p]) {
               const C c = gslot ? c1[p] : c0[p];
@@ -283,10 +326,10 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
 #pragma unroll
     for (int b = 0; b < MAXP; ++b) {
       if (b < nl) {
-        const int dst = loads[nxt.x + b].y;
+        const int4 ld = loads[nxt.x + b];
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
-          if (tid + 256 * q < P) L[dst + tid + 256 * q] = stg[b][q];
+          if (sv[q]) L[ld.y + db[q] + ld.z * ddx[q] + ld.w * ddy[q]] = stg[b][q];
       }
     }
     if (nl > MAXP) stage_sync(nxt.x, MAXP, nl);
@@ -300,13 +343,8 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
 
 // ------------------------------------------------------------ variants
 namespace {
-constexpr TileShape kVariants[] = {
-    // large moment orders (up to 39 staged in registers)
-    {32, 4, 40}, {64, 2, 40}, {32, 2, 40},
-    // medium orders (up to 15)
-    {32, 4, 16}, {64, 4, 16}, {32, 8, 16}, {64, 2, 16},
-    // small orders (up to 7)
-    {32, 4, 8}, {64, 4, 8}, {32, 8, 8}, {64, 8, 8}};
+constexpr TileShape kVariants[] = {{64, 4, 10}, {128, 2, 10}, {32, 8, 10}, {32, 16, 10},
+                                   {128, 4, 10}, {64, 8, 10}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <typename T, int TX, int TY, int CAP>
@@ -323,7 +361,7 @@ hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
   sc.py = a.py;
   sc.ntx = a.ntx;
   sc.nty = a.nty;
-  sc.norders = a.norders;
+  sc.nchunks = a.nchunks;
   sc.zero_off = a.zero_off;
   sc.parity = a.parity;
   sc.tau = a.tau;
@@ -340,26 +378,21 @@ hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
     if (e != hipSuccess) return e;
     attr_bytes = size_t(max_lds);
   }
-  const int blocks = a.ntx * a.nty;
+  const int blocks = a.ntx * a.nty * a.nchunks;
   hipLaunchKernelGGL((sweep_kernel<T, TX, TY, CAP>), dim3(blocks), dim3(256), lds, stream,
-                     reinterpret_cast<T*>(a.u), a.decay, a.orders, a.loads, a.rows, a.rcoef, sc);
+                     reinterpret_cast<T*>(a.u), a.decay, a.chunks, a.orders, a.loads, a.rows, a.rcoef, sc);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_typed(int variant, const void* args, int slots, hipStream_t stream) {
   switch (variant) {
-    case 0: return launch_t<T, 32, 4, 40>(args, slots, stream);
-    case 1: return launch_t<T, 64, 2, 40>(args, slots, stream);
-    case 2: return launch_t<T, 32, 2, 40>(args, slots, stream);
-    case 3: return launch_t<T, 32, 4, 16>(args, slots, stream);
-    case 4: return launch_t<T, 64, 4, 16>(args, slots, stream);
-    case 5: return launch_t<T, 32, 8, 16>(args, slots, stream);
-    case 6: return launch_t<T, 64, 2, 16>(args, slots, stream);
-    case 7: return launch_t<T, 32, 4, 8>(args, slots, stream);
-    case 8: return launch_t<T, 64, 4, 8>(args, slots, stream);
-    case 9: return launch_t<T, 32, 8, 8>(args, slots, stream);
-    case 10: return launch_t<T, 64, 8, 8>(args, slots, stream);
+    case 0: return launch_t<T, 64, 4, 10>(args, slots, stream);
+    case 1: return launch_t<T, 128, 2, 10>(args, slots, stream);
+    case 2: return launch_t<T, 32, 8, 10>(args, slots, stream);
+    case 3: return launch_t<T, 32, 16, 10>(args, slots, stream);
+    case 4: return launch_t<T, 128, 4, 10>(args, slots, stream);
+    case 5: return launch_t<T, 64, 8, 10>(args, slots, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -368,11 +401,6 @@ hipError_t launch_typed(int variant, const void* args, int slots, hipStream_t st
 int sweep_variant_count() { return kNumVariants; }
 TileShape sweep_variant(int v) { return kVariants[v]; }
 
-int sweep_cap_for(int N) {
-  if (N + 1 <= 8) return 8;
-  if (N + 1 <= 16) return 16;
-  return 40;
-}
 
 size_t sweep_lds_bytes(int v, int slots, int storage) {
   const size_t s = storage == STORE_FP64 ? 8 : storage == STORE_FP32 ? 4 : 2;

@@ -81,25 +81,29 @@ def test_c1_line_source_fp64_full_run():
 
 
 @pytest.mark.parametrize("N", [5, 13, 39])
-def test_tile_variants_are_bitwise_identical(N):
-    """Every compiled tile variant (register capacity classes included) gives
-    the same bits: the arithmetic per point does not depend on the tiling."""
+def test_tile_variants_are_bitwise_identical(N, monkeypatch):
+    """Every compiled tile variant and every split of the moments into m
+    ranges gives the same bits: the arithmetic per point does not depend on
+    the tiling."""
     prob = wl.checkerboard(N=N, n=77, t_final=0.5)
     ref = None
-    for v in range(11):
-        s = pa.Solver.from_problem(prob)
-        s.bind_torch()
-        try:
-            s.set_variant(v)
-        except pa.StarmapError:
-            continue
-        s.advance(9)
-        out = s.moments()
-        if ref is None:
-            ref = out
-        else:
-            for a, b in zip(out, ref):
-                assert np.array_equal(a, b), f"variant {v} differs"
+    for width in (2, 5, 8, 12):
+        monkeypatch.setenv("STARMAP_CHUNK_WIDTH", str(width))
+        for v in range(6):
+            s = pa.Solver.from_problem(prob)
+            s.bind_torch()
+            try:
+                s.set_variant(v)
+            except pa.StarmapError:
+                continue
+            s.advance(9)
+            out = s.moments()
+            if ref is None:
+                ref = out
+            else:
+                for a, b in zip(out, ref):
+                    assert np.array_equal(a, b), f"variant {v} width {width} differs"
+    assert ref is not None
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])

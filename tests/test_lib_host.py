@@ -111,3 +111,15 @@ def test_sweep_bytes_counts_every_plane():
     # odd sweep: 420 odd planes read+written, 400 even planes read (~1e6 points each)
     assert 4.0 * (2 * 420 + 400) * 1.0e6 < b_odd < 4.0 * (2 * 420 + 400 + 4) * 1.002e6
     assert 4.0 * (2 * 400 + 420) * 1.0e6 < b_even < 4.0 * (2 * 400 + 420 + 4) * 1.002e6
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7, 9, 10, 11, 15, 20, 31, 39, 60])
+@pytest.mark.parametrize("tile", [(64, 4), (128, 2), (32, 8), (32, 16), (128, 4), (64, 8)])
+def test_sweep_programs_are_consistent(N, tile):
+    """Replay of the staged LDS window: every coupling of every row reads the
+    plane the moment matrices name, for every m-range split."""
+    from paper_1211_2205_amd import _binding as B
+    L = pa.lib()
+    for nchunks in sorted({1, 2, 3, 4, max(1, (N + 1) // 10), (N + 1) // 2 or 1}):
+        rc = L.starmap_plan_check(N, tile[0], tile[1], nchunks)
+        assert rc == 0, (N, tile, nchunks, L.starmap_last_error())
