@@ -231,6 +231,46 @@ int starmap_sweep_bytes(const starmap_solver* s, int32_t parity, double* bytes);
 int starmap_profile_begin(starmap_solver* s);
 int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches, double* bytes);
 
+/* Restore the initial condition at t = 0 (step 0) on the device. */
+int starmap_reset(starmap_solver* s);
+
+/* ------------------------------------------------------------------- batches */
+
+/* A batch advances several independent solvers together on one device:
+   sweep number j of the fused composition (see starmap_advance; sweep j is
+   odd for even j) runs as ONE kernel launch over the tiles of every instance
+   that still has sweeps left, so instances of different orders N, grid sizes
+   and step counts share the machine, and a whole run is captured in one HIP
+   graph.  The solvers must share the storage precision, have time-independent
+   data, and outlive the batch; their results are read with the per-solver
+   calls.  While in a batch, a solver's tile variant is the batch's: do not
+   call starmap_set_variant on it. */
+typedef struct starmap_batch starmap_batch;
+
+/* count >= 1 distinct solvers.  The array is copied. */
+int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_batch** out);
+void starmap_batch_destroy(starmap_batch* b);
+
+/* Advance every solver from its current step to t_final and synchronise.
+   use_graph != 0 captures the launches in a HIP graph (kept and relaunched
+   while the launch plan is unchanged); 0 launches them one by one.  Results
+   are bitwise equal to starmap_run on each solver with the same tile. */
+int starmap_batch_run(starmap_batch* b, int32_t use_graph);
+
+/* The last run: device time between events around its launches (ms), cell-
+   moment updates (sum of nx ny N_mom steps), algorithmic bytes (sum of
+   starmap_sweep_bytes over its sweeps), and kernel launches. */
+int starmap_batch_last_run(const starmap_batch* b, double* ms, int64_t* updates, double* bytes,
+                           int64_t* launches);
+
+/* Tile variant and m-range width (4, 6 or 8) shared by the batch; the default
+   is variant 0 with width 8.  starmap_batch_autotune times every pair that
+   fits on a few sub-step-0 sweeps of the whole batch (state unchanged) and
+   keeps the fastest. */
+int starmap_batch_set_variant(starmap_batch* b, int32_t variant, int32_t width);
+int starmap_batch_get_variant(const starmap_batch* b, int32_t* variant, int32_t* width);
+int starmap_batch_autotune(starmap_batch* b, int32_t sweeps_per_variant);
+
 const char* starmap_last_error(void);
 
 #ifdef __cplusplus

@@ -79,6 +79,14 @@ SIGNATURES = [
     ("starmap_sweep_bytes", [_vp, ctypes.c_int32, _dp], ctypes.c_int),
     ("starmap_profile_begin", [_vp], ctypes.c_int),
     ("starmap_profile_end", [_vp, _dp, _i64p, _dp], ctypes.c_int),
+    ("starmap_reset", [_vp], ctypes.c_int),
+    ("starmap_batch_create", [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp)], ctypes.c_int),
+    ("starmap_batch_destroy", [_vp], None),
+    ("starmap_batch_run", [_vp, ctypes.c_int32], ctypes.c_int),
+    ("starmap_batch_last_run", [_vp, _dp, _i64p, _dp, _i64p], ctypes.c_int),
+    ("starmap_batch_set_variant", [_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    ("starmap_batch_get_variant", [_vp, _i32p, _i32p], ctypes.c_int),
+    ("starmap_batch_autotune", [_vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_last_error", [], ctypes.c_char_p),
 ]
 

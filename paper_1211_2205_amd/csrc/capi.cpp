@@ -414,6 +414,23 @@ int default_variant(const starmap_solver* s) {
   return -1;
 }
 
+// initial state planes (zero where no initial field is set)
+int upload_initial(starmap_solver* s) {
+  HIP_TRY(hipMemsetAsync(dptr(s, s->off_state), 0, size_t(s->nmom) * s->plane_bytes_state(), s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < s->nmom; ++k) {
+    auto it = s->initial.find(k);
+    if (it == s->initial.end() || !it->second.set()) continue;
+    std::vector<double> v;
+    int rc = sample(s, it->second, s->moms[k].gx, s->moms[k].gy, 0.0, v);
+    if (rc) return rc;
+    rc = upload_plane(s, dptr(s, s->off_state + size_t(k) * s->plane_bytes_state()), s->moms[k].gx,
+                      s->moms[k].gy, v.data(), false);
+    if (rc) return rc;
+  }
+  return STARMAP_OK;
+}
+
 int ensure_device(starmap_solver* s) {
   if (s->device_ready) return STARMAP_OK;
   int rc = ensure_stream(s);
@@ -425,16 +442,8 @@ int ensure_device(starmap_solver* s) {
   // zero everything once (padding included), then the initial state
   HIP_TRY(hipMemsetAsync(s->dev, 0, s->dev_bytes, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  for (int k = 0; k < s->nmom; ++k) {
-    auto it = s->initial.find(k);
-    if (it == s->initial.end() || !it->second.set()) continue;
-    std::vector<double> v;
-    rc = sample(s, it->second, s->moms[k].gx, s->moms[k].gy, 0.0, v);
-    if (rc) return rc;
-    rc = upload_plane(s, dptr(s, s->off_state + size_t(k) * s->plane_bytes_state()), s->moms[k].gx,
-                      s->moms[k].gy, v.data(), false);
-    if (rc) return rc;
-  }
+  rc = upload_initial(s);
+  if (rc) return rc;
   // diagnostics geometry: valid points per plane
   {
     std::vector<int32_t> geo(size_t(s->nmom) * 2);
@@ -1124,6 +1133,390 @@ double sweep_bytes_of(const starmap_solver* s, int parity) {
 
 extern "C" const char* starmap_last_error(void) { return g_last_error.c_str(); }
 
+extern "C" int starmap_reset(starmap_solver* s) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (s->device_ready) {
+    int rc = upload_initial(s);
+    if (rc) return rc;
+  }
+  s->t = 0.0;
+  s->steps_done = 0;
+  if (s->time_dependent) s->materials_ready = false;
+  return STARMAP_OK;
+}
+
+// ------------------------------------------------------------ batches
+// A batch advances several independent solvers together: every sweep number
+// j of the fused composition is one launch over the workgroups of all
+// instances still running, and the whole run is one HIP graph.
+
+struct starmap_batch {
+  std::vector<starmap_solver*> inst;  // as given by the caller
+  int storage = STORE_FP64;
+  int variant = -1, width = 0;  // one tile variant and m-range width for all instances
+  int slots = 0;                // LDS planes of the largest instance
+  bool tiles_set = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  void* dtab = nullptr;  // BatchEntry[count], then int first[count + 1]
+  // launch plan of the current table: sorted instances, sweeps, workgroup prefix
+  std::vector<int> order;
+  std::vector<int> nsweeps;
+  std::vector<int> first;
+  // captured run
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> graph_key;
+  // last run
+  double last_ms = 0.0, last_bytes = 0.0;
+  int64_t last_updates = 0, last_launches = 0;
+};
+
+namespace {
+
+size_t batch_table_bytes(int count) { return align256(size_t(count) * sizeof(BatchEntry)) + size_t(count + 1) * 4; }
+
+int max_lds_bytes() {
+  int dev = 0, max_lds = 64 * 1024;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int x = 0;
+    if (hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && x > 0) max_lds = x;
+  }
+  return max_lds;
+}
+
+void drop_graph(starmap_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_key.clear();
+}
+
+// Device workspaces and materials of every instance.
+int batch_devices(starmap_batch* b) {
+  for (auto* s : b->inst) {
+    int rc = ensure_device(s);
+    if (rc) return rc;
+    if (!s->materials_ready) {
+      rc = upload_materials(s, s->t + 0.5 * s->dt);
+      if (rc) return rc;
+    }
+  }
+  return STARMAP_OK;
+}
+
+// ... and the shared tile of every instance.
+int batch_prepare(starmap_batch* b, int variant, int width) {
+  int rc = batch_devices(b);
+  if (rc) return rc;
+  if (b->tiles_set && variant == b->variant && width == b->width) return STARMAP_OK;
+  const int max_lds = max_lds_bytes();
+  int slots = 0;
+  for (auto* s : b->inst) {
+    s->variant = variant;
+    s->chunk_width = width;
+    rc = upload_program(s);
+    if (rc) return rc;
+    if (s->prog[0].chunks.size() != s->prog[1].chunks.size())
+      return fail(STARMAP_ESTATE, "sweep programs of the two parities differ in m ranges");
+    slots = std::max(slots, s->slots);
+  }
+  b->tiles_set = true;
+  b->variant = variant;
+  b->width = width;
+  b->slots = slots;
+  drop_graph(b);
+  if (sweep_lds_bytes(variant, slots, b->storage) > size_t(max_lds))
+    return fail(STARMAP_EINVAL, "tile variant does not fit the LDS for the largest moment order of the batch");
+  HIP_TRY(prepare_sweep(b->storage, variant, slots));
+  return STARMAP_OK;
+}
+
+int items_of(const starmap_solver* s) {
+  const TileShape ts = sweep_variant(s->variant);
+  const int ntx = (s->nx + 1 + ts.tx - 1) / ts.tx, nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
+  return ntx * nty * int(s->prog[0].chunks.size());
+}
+
+// Entries of the instances with sweeps[i] > 0, sorted by sweeps (descending,
+// stable), uploaded with their workgroup prefix.  zero_tau: every sub-step
+// length 0 (timing on live state leaves it unchanged).
+int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau) {
+  const int count = int(b->inst.size());
+  std::vector<int> ord;
+  for (int i = 0; i < count; ++i)
+    if (sweeps[i] > 0) ord.push_back(i);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sweeps[x] > sweeps[y]; });
+  std::vector<BatchEntry> tab(ord.size());
+  std::vector<int> first(ord.size() + 1, 0);
+  int64_t total = 0;
+  for (size_t r = 0; r < ord.size(); ++r) {
+    starmap_solver* s = b->inst[ord[r]];
+    BatchEntry& e = tab[r];
+    std::memset(&e, 0, sizeof(e));
+    e.u = dptr(s, s->off_state);
+    e.decay = dptr(s, s->off_decay);
+    for (int p = 0; p < 2; ++p) {
+      const auto& pr = s->prog[p];
+      char* base = dptr(s, s->off_prog[p]);
+      size_t o = 0;
+      e.chunks[p] = reinterpret_cast<const int4*>(base + o);
+      o += align256(pr.chunks.size() * 16);
+      e.orders[p] = reinterpret_cast<const int4*>(base + o);
+      o += align256(pr.orders.size() * 16);
+      e.loads[p] = reinterpret_cast<const int4*>(base + o);
+      o += align256(pr.loads.size() * 16);
+      e.rows[p] = reinterpret_cast<const int*>(base + o);
+      o += align256(pr.rows.size() * 64);
+      e.rcoef[p] = base + o;
+      e.zero_off[p] = pr.zero_off;
+    }
+    e.plane_stride = s->plane_stride;
+    e.tau_full = zero_tau ? 0.0 : s->dt;
+    e.tau_half = zero_tau ? 0.0 : 0.5 * s->dt;
+    e.pitch = s->pitch;
+    e.nx = s->nx;
+    e.ny = s->ny;
+    e.px = s->px;
+    e.py = s->py;
+    const TileShape ts = sweep_variant(s->variant);
+    e.ntx = (s->nx + 1 + ts.tx - 1) / ts.tx;
+    e.nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
+    e.nchunks = int(s->prog[0].chunks.size());
+    e.nsweeps = sweeps[ord[r]];
+    first[r] = int(total);
+    total += items_of(s);
+  }
+  if (total >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "too many workgroups in one batched sweep");
+  first[ord.size()] = int(total);
+  std::vector<char> buf(batch_table_bytes(count), 0);
+  std::memcpy(buf.data(), tab.data(), tab.size() * sizeof(BatchEntry));
+  std::memcpy(buf.data() + align256(size_t(count) * sizeof(BatchEntry)), first.data(), first.size() * 4);
+  HIP_TRY(hipMemcpyAsync(b->dtab, buf.data(), buf.size(), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->order = ord;
+  b->nsweeps.resize(ord.size());
+  for (size_t r = 0; r < ord.size(); ++r) b->nsweeps[r] = sweeps[ord[r]];
+  b->first = first;
+  return STARMAP_OK;
+}
+
+// Queue sweeps j0 .. j1-1 of the current table on the batch stream.
+int batch_launch(starmap_batch* b, int j0, int j1) {
+  const BatchEntry* tab = reinterpret_cast<const BatchEntry*>(b->dtab);
+  const int* first =
+      reinterpret_cast<const int*>(static_cast<char*>(b->dtab) + align256(b->inst.size() * sizeof(BatchEntry)));
+  int n_active = int(b->nsweeps.size());
+  for (int j = j0; j < j1; ++j) {
+    while (n_active > 0 && b->nsweeps[n_active - 1] <= j) --n_active;
+    if (n_active == 0) break;
+    HIP_TRY(launch_sweep_batch(b->storage, b->variant, tab, first, n_active, b->first[n_active], j, b->slots,
+                               b->stream));
+  }
+  return STARMAP_OK;
+}
+
+int batch_sync_solvers(starmap_batch* b) {
+  for (auto* s : b->inst) HIP_TRY(hipStreamSynchronize(s->stream));
+  return STARMAP_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_batch** out) {
+  if (!out) return fail(STARMAP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!solvers || count < 1) return fail(STARMAP_EINVAL, "empty batch");
+  std::vector<starmap_solver*> v(solvers, solvers + count);
+  for (int i = 0; i < count; ++i) {
+    if (!v[i]) return fail(STARMAP_EINVAL, "NULL solver in batch");
+    if (v[i]->time_dependent) return fail(STARMAP_EINVAL, "batched solvers need time-independent data");
+    if (v[i]->storage != v[0]->storage) return fail(STARMAP_EINVAL, "batched solvers need one storage precision");
+  }
+  {
+    std::vector<starmap_solver*> u = v;
+    std::sort(u.begin(), u.end());
+    if (std::adjacent_find(u.begin(), u.end()) != u.end()) return fail(STARMAP_EINVAL, "solver listed twice");
+  }
+  auto b = std::make_unique<starmap_batch>();
+  b->inst = v;
+  b->storage = v[0]->storage;
+  HIP_TRY(hipStreamCreate(&b->stream));
+  HIP_TRY(hipEventCreate(&b->ev[0]));
+  HIP_TRY(hipEventCreate(&b->ev[1]));
+  HIP_TRY(hipMalloc(&b->dtab, batch_table_bytes(count)));
+  *out = b.release();
+  return STARMAP_OK;
+}
+
+void starmap_batch_destroy(starmap_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  if (b->dtab) (void)hipFree(b->dtab);
+  for (auto& e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+int starmap_batch_set_variant(starmap_batch* b, int32_t variant, int32_t width) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  if (variant < 0 || variant >= sweep_variant_count()) return fail(STARMAP_EINVAL, "unknown variant");
+  if (std::find(std::begin(kChunkWidths), std::end(kChunkWidths), width) == std::end(kChunkWidths))
+    return fail(STARMAP_EINVAL, "unsupported m-range width");
+  return batch_prepare(b, variant, width);
+}
+
+int starmap_batch_get_variant(const starmap_batch* b, int32_t* variant, int32_t* width) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  if (variant) *variant = b->tiles_set ? b->variant : -1;
+  if (width) *width = b->tiles_set ? b->width : 0;
+  return STARMAP_OK;
+}
+
+int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  int rc = batch_prepare(b, b->tiles_set ? b->variant : 0, b->tiles_set ? b->width : kDefaultChunkWidth);
+  if (rc) return rc;
+  rc = batch_sync_solvers(b);
+  if (rc) return rc;
+  const int count = int(b->inst.size());
+  std::vector<int> sweeps(count);
+  int64_t updates = 0;
+  double bytes = 0.0;
+  for (int i = 0; i < count; ++i) {
+    starmap_solver* s = b->inst[i];
+    const int64_t n = s->steps_total - s->steps_done;
+    if (2 * n + 1 >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "too many steps for one batched run");
+    sweeps[i] = n > 0 ? int(2 * n + 1) : 0;
+    updates += int64_t(s->nmom) * s->nx * s->ny * n;
+    if (n > 0) bytes += double(n + 1) * sweep_bytes_of(s, 1) + double(n) * sweep_bytes_of(s, 0);
+  }
+  rc = batch_table(b, sweeps, false);
+  if (rc) return rc;
+  const int jmax = b->nsweeps.empty() ? 0 : b->nsweeps[0];
+  int64_t launches = 0;
+  {
+    int na = int(b->nsweeps.size());
+    for (int j = 0; j < jmax; ++j) {
+      while (na > 0 && b->nsweeps[na - 1] <= j) --na;
+      launches += na > 0;
+    }
+  }
+  HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+  if (jmax > 0) {
+    if (use_graph) {
+      // the graph depends on the tile (kernel, LDS) and on the launch plan
+      std::vector<int> key = {b->variant, b->width, b->slots};
+      key.insert(key.end(), b->nsweeps.begin(), b->nsweeps.end());
+      key.insert(key.end(), b->first.begin(), b->first.end());
+      if (!b->exec || key != b->graph_key) {
+        drop_graph(b);
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        rc = batch_launch(b, 0, jmax);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (rc) {
+          if (g) (void)hipGraphDestroy(g);
+          return rc;
+        }
+        HIP_TRY(e);
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_key = key;
+        // time the graph launch, not the capture
+        HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+      }
+      HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    } else {
+      rc = batch_launch(b, 0, jmax);
+      if (rc) return rc;
+    }
+  }
+  HIP_TRY(hipEventRecord(b->ev[1], b->stream));
+  HIP_TRY(hipEventSynchronize(b->ev[1]));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+  for (auto* s : b->inst) {
+    s->steps_done = s->steps_total;
+    s->t = double(s->steps_done) * s->dt;
+  }
+  b->last_ms = ms;
+  b->last_updates = updates;
+  b->last_bytes = bytes;
+  b->last_launches = launches;
+  return STARMAP_OK;
+}
+
+int starmap_batch_last_run(const starmap_batch* b, double* ms, int64_t* updates, double* bytes, int64_t* launches) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  if (ms) *ms = b->last_ms;
+  if (updates) *updates = b->last_updates;
+  if (bytes) *bytes = b->last_bytes;
+  if (launches) *launches = b->last_launches;
+  return STARMAP_OK;
+}
+
+int starmap_batch_autotune(starmap_batch* b, int32_t sweeps) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  if (sweeps < 1) sweeps = 1;
+  const int count = int(b->inst.size());
+  const int max_lds = max_lds_bytes();
+  {
+    int rc = batch_devices(b);
+    if (rc) return rc;
+  }
+  int best_v = -1, best_w = 0;
+  float best_ms = 0.f;
+  std::vector<std::vector<int>> tried;
+  for (int w : kChunkWidths) {
+    std::vector<int> split;
+    for (auto* s : b->inst) split.push_back(sweep_chunk_count(s->N, w));
+    if (std::find(tried.begin(), tried.end(), split) != tried.end()) continue;  // same m ranges as a narrower width
+    tried.push_back(split);
+    for (int v = 0; v < sweep_variant_count(); ++v) {
+      // LDS check before the kernels are opted in
+      int slots = 0;
+      for (auto* s : b->inst) {
+        s->variant = v;
+        s->chunk_width = w;
+        int rc = upload_program(s);
+        if (rc) return rc;
+        slots = std::max(slots, s->slots);
+      }
+      b->tiles_set = false;
+      if (sweep_lds_bytes(v, slots, b->storage) > size_t(max_lds)) continue;
+      int rc = batch_prepare(b, v, w);
+      if (rc) return rc;
+      // tau = 0 leaves every value unchanged; three sweeps: odd, even, odd
+      rc = batch_table(b, std::vector<int>(count, 3), true);
+      if (!rc) rc = batch_launch(b, 1, 3);
+      if (rc) return rc;
+      HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+      for (int i = 0; i < sweeps && !rc; ++i) rc = batch_launch(b, 1, 3);
+      if (rc) return rc;
+      HIP_TRY(hipEventRecord(b->ev[1], b->stream));
+      HIP_TRY(hipEventSynchronize(b->ev[1]));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+      if (std::getenv("STARMAP_VERBOSE")) {
+        const TileShape ts = sweep_variant(v);
+        std::fprintf(stderr, "starmap batch autotune: width %d variant %d (%dx%d) %.3f ms per sweep pair\n", w, v,
+                     ts.tx, ts.ty, ms / sweeps);
+      }
+      if (best_v < 0 || ms < best_ms) {
+        best_v = v;
+        best_w = w;
+        best_ms = ms;
+      }
+    }
+  }
+  if (best_v < 0) return fail(STARMAP_ENOMEM, "no sweep tile fits the LDS for this batch");
+  return batch_prepare(b, best_v, best_w);
+}
 
 }  // extern "C"

@@ -44,6 +44,33 @@ size_t sweep_lds_bytes(int v, int slots, int storage);
 // Launch one sweep; args.u etc. must be device pointers.  Returns a HIP error.
 hipError_t launch_sweep(int storage, int variant, const void* args, int slots, hipStream_t stream);
 
+// One instance of a batched run: device pointers of its state, decay planes
+// and the sweep programs of both parities, and its scalars.
+struct BatchEntry {
+  void* u;
+  const void* decay;  // compute type
+  const int4* chunks[2];
+  const int4* orders[2];
+  const int4* loads[2];
+  const int* rows[2];
+  const void* rcoef[2];  // compute type
+  int64_t plane_stride;
+  double tau_full, tau_half;  // dt and dt / 2
+  int pitch, nx, ny, px, py, ntx, nty, nchunks;
+  int zero_off[2];
+  int nsweeps;  // sweeps still to run: 2 n + 1 for n steps
+  int pad;
+};
+
+// Opts the kernels of a variant in to the LDS it needs (outside any stream
+// capture).  Returns a HIP error.
+hipError_t prepare_sweep(int storage, int variant, int slots);
+
+// Launch sweep number j of a batched run over the first n_active instances of
+// table, whose workgroups are numbered from first[i]; items = first[n_active].
+hipError_t launch_sweep_batch(int storage, int variant, const BatchEntry* table, const int* first, int n_active,
+                              int items, int j, int slots, hipStream_t stream);
+
 // FP64 diagnostics of a state: mass of plane 0 (times cell area is applied on
 // the host), sum of squares and max |u| over all valid points, count of
 // non-finite values.  part must hold 4 * nblocks doubles, out 4 doubles.

@@ -20,6 +20,7 @@
 // periodic, clamp for extrapolation), so the stencil itself is uniform.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -90,13 +91,14 @@ struct SweepScalars {
   C tau;
 };
 
+// Body of one workgroup's work in a sweep: spatial tile and m range number lb
+// (lb = tile * nchunks + range) of one instance.
 template <typename T, int TX, int TY, int CAP>
-__global__ void __launch_bounds__(256)
-sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
-             const int4* __restrict__ chunks, const int4* __restrict__ orders,
-             const int4* __restrict__ loads, const int* __restrict__ rows,
-             const typename ComputeOf<T>::type* __restrict__ rcoef,
-             const SweepScalars<typename ComputeOf<T>::type> a) {
+__device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
+                                           const int4* __restrict__ chunks, const int4* __restrict__ orders,
+                                           const int4* __restrict__ loads, const int* __restrict__ rows,
+                                           const typename ComputeOf<T>::type* __restrict__ rcoef,
+                                           const SweepScalars<typename ComputeOf<T>::type>& a, const int lb) {
   using C = typename ComputeOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   T* L = reinterpret_cast<T*>(smem);
@@ -115,9 +117,6 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
   constexpr int EPT = PPT + 1;                 // staged points per thread and plane: interior + halo
 
   const int tid = threadIdx.x;
-  // logical block = tile * nchunks + chunk: the m ranges of one tile run on
-  // the same XCD, one after another, and share its L2
-  const int lb = xcd_tile(blockIdx.x, gridDim.x);
   const int tile = lb / a.nchunks;
   const int4 chk = chunks[lb - tile * a.nchunks];
   if (chk.x >= chk.y) return;  // no output rows in this m range
@@ -341,17 +340,116 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
   }
 }
 
+template <typename T, int TX, int TY, int CAP>
+__global__ void __launch_bounds__(256)
+sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
+             const int4* __restrict__ chunks, const int4* __restrict__ orders,
+             const int4* __restrict__ loads, const int* __restrict__ rows,
+             const typename ComputeOf<T>::type* __restrict__ rcoef,
+             const SweepScalars<typename ComputeOf<T>::type> a) {
+  // logical block = tile * nchunks + chunk: the m ranges of one tile run on
+  // the same XCD, one after another, and share its L2
+  sweep_tile<T, TX, TY, CAP>(U, decay, chunks, orders, loads, rows, rcoef, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Sweep number j of a batched run.  Instances are sorted by their number of
+// sweeps (descending), so the instances still running at sweep j are the
+// first n_active; their workgroups (tiles x m ranges) are numbered
+// consecutively, instance i owning [first[i], first[i+1]).  Sweep j has odd
+// parity for even j (the composition starts and ends with odd half-steps).
+// BatchEntry as the device reads it: pointers read from memory carry no
+// address space, so without this the compiler would use flat accesses (which
+// share the LDS wait counter) and vector loads for the uniform tables.
+template <typename P>
+using gptr = __attribute__((address_space(1))) P*;
+struct BatchEntryG {
+  gptr<void> u;
+  gptr<const void> decay;
+  gptr<const int4> chunks[2];
+  gptr<const int4> orders[2];
+  gptr<const int4> loads[2];
+  gptr<const int> rows[2];
+  gptr<const void> rcoef[2];
+  int64_t plane_stride;
+  double tau_full, tau_half;
+  int pitch, nx, ny, px, py, ntx, nty, nchunks;
+  int zero_off[2];
+  int nsweeps;
+  int pad;
+};
+static_assert(sizeof(BatchEntryG) == sizeof(BatchEntry), "device view of BatchEntry");
+static_assert(offsetof(BatchEntryG, plane_stride) == offsetof(BatchEntry, plane_stride), "device view of BatchEntry");
+static_assert(offsetof(BatchEntryG, nsweeps) == offsetof(BatchEntry, nsweeps), "device view of BatchEntry");
+
+template <typename T, int TX, int TY, int CAP>
+__global__ void __launch_bounds__(256)
+sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__ first, const int n_active,
+                   const int j) {
+  using C = typename ComputeOf<T>::type;
+  const int item = xcd_tile(blockIdx.x, gridDim.x);
+  int lo = 0, hi = n_active - 1;  // last instance with first[i] <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  const BatchEntryG& e = reinterpret_cast<const BatchEntryG*>(table)[lo];
+  const int par = (j & 1) ? 0 : 1;
+  SweepScalars<C> a;
+  a.plane_stride = e.plane_stride;
+  a.pitch = e.pitch;
+  a.nx = e.nx;
+  a.ny = e.ny;
+  a.px = e.px;
+  a.py = e.py;
+  a.ntx = e.ntx;
+  a.nty = e.nty;
+  a.nchunks = e.nchunks;
+  a.zero_off = e.zero_off[par];
+  a.parity = par;
+  a.tau = C((j == 0 || j == e.nsweeps - 1) ? e.tau_half : e.tau_full);
+  sweep_tile<T, TX, TY, CAP>((T*)(gptr<T>)e.u, (const C*)(gptr<const C>)e.decay, (const int4*)e.chunks[par],
+                             (const int4*)e.orders[par], (const int4*)e.loads[par], (const int*)e.rows[par],
+                             (const C*)(gptr<const C>)e.rcoef[par], a, item - first[lo]);
+}
+
 // ------------------------------------------------------------ variants
 namespace {
 constexpr TileShape kVariants[] = {{64, 4, 10}, {128, 2, 10}, {32, 8, 10}, {32, 16, 10},
                                    {128, 4, 10}, {64, 8, 10}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
+// Opt the kernels of one instantiation in to all of the device's LDS (once).
+template <typename T, int TX, int TY, int CAP>
+hipError_t prepare_t(size_t lds) {
+  static size_t attr_bytes = 0;
+  if (lds <= attr_bytes) return hipSuccess;
+  int dev = 0, max_lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  if (lds > size_t(max_lds)) return hipErrorInvalidValue;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<T, TX, TY, CAP>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_batch_kernel<T, TX, TY, CAP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e != hipSuccess) return e;
+  attr_bytes = size_t(max_lds);
+  return hipSuccess;
+}
+
+template <typename T, int TX, int TY, int CAP>
+size_t lds_t(int slots) {
+  return size_t(slots) * (TX + 1) * (TY + 1) * sizeof(T);
+}
+
 template <typename T, int TX, int TY, int CAP>
 hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   const auto& a = *reinterpret_cast<const SweepArgs<C>*>(args);
-  const size_t lds = size_t(slots) * (TX + 1) * (TY + 1) * sizeof(T);
+  const size_t lds = lds_t<T, TX, TY, CAP>(slots);
+  hipError_t e = prepare_t<T, TX, TY, CAP>(lds);
+  if (e != hipSuccess) return e;
   SweepScalars<C> sc;
   sc.plane_stride = a.plane_stride;
   sc.pitch = a.pitch;
@@ -365,37 +463,57 @@ hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
   sc.zero_off = a.zero_off;
   sc.parity = a.parity;
   sc.tau = a.tau;
-  static size_t attr_bytes = 0;
-  if (lds > attr_bytes) {
-    // opt in to more than the default dynamic LDS once per instantiation
-    int dev = 0, max_lds = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) return e;
-    if (lds > size_t(max_lds)) return hipErrorInvalidValue;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sweep_kernel<T, TX, TY, CAP>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e != hipSuccess) return e;
-    attr_bytes = size_t(max_lds);
-  }
   const int blocks = a.ntx * a.nty * a.nchunks;
   hipLaunchKernelGGL((sweep_kernel<T, TX, TY, CAP>), dim3(blocks), dim3(256), lds, stream,
                      reinterpret_cast<T*>(a.u), a.decay, a.chunks, a.orders, a.loads, a.rows, a.rcoef, sc);
   return hipGetLastError();
 }
 
+template <typename T, int TX, int TY, int CAP>
+hipError_t launch_batch_t(const BatchEntry* table, const int* first, int n_active, int items, int j, int slots,
+                          hipStream_t stream) {
+  const size_t lds = lds_t<T, TX, TY, CAP>(slots);
+  hipError_t e = prepare_t<T, TX, TY, CAP>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((sweep_batch_kernel<T, TX, TY, CAP>), dim3(items), dim3(256), lds, stream, table, first,
+                     n_active, j);
+  return hipGetLastError();
+}
+
+// the compiled tile variants, in the order of kVariants
+#define STARMAP_FOR_VARIANT(v, CALL)      \
+  switch (v) {                            \
+    case 0: return CALL(64, 4, 10);       \
+    case 1: return CALL(128, 2, 10);      \
+    case 2: return CALL(32, 8, 10);       \
+    case 3: return CALL(32, 16, 10);      \
+    case 4: return CALL(128, 4, 10);      \
+    case 5: return CALL(64, 8, 10);       \
+  }                                       \
+  return hipErrorInvalidValue;
+
 template <typename T>
 hipError_t launch_typed(int variant, const void* args, int slots, hipStream_t stream) {
-  switch (variant) {
-    case 0: return launch_t<T, 64, 4, 10>(args, slots, stream);
-    case 1: return launch_t<T, 128, 2, 10>(args, slots, stream);
-    case 2: return launch_t<T, 32, 8, 10>(args, slots, stream);
-    case 3: return launch_t<T, 32, 16, 10>(args, slots, stream);
-    case 4: return launch_t<T, 128, 4, 10>(args, slots, stream);
-    case 5: return launch_t<T, 64, 8, 10>(args, slots, stream);
-  }
-  return hipErrorInvalidValue;
+#define STARMAP_CALL(X, Y, K) launch_t<T, X, Y, K>(args, slots, stream)
+  STARMAP_FOR_VARIANT(variant, STARMAP_CALL)
+#undef STARMAP_CALL
 }
+
+template <typename T>
+hipError_t launch_batch_typed(int variant, const BatchEntry* table, const int* first, int n_active, int items,
+                              int j, int slots, hipStream_t stream) {
+#define STARMAP_CALL(X, Y, K) launch_batch_t<T, X, Y, K>(table, first, n_active, items, j, slots, stream)
+  STARMAP_FOR_VARIANT(variant, STARMAP_CALL)
+#undef STARMAP_CALL
+}
+
+template <typename T>
+hipError_t prepare_typed(int variant, int slots) {
+#define STARMAP_CALL(X, Y, K) prepare_t<T, X, Y, K>(lds_t<T, X, Y, K>(slots))
+  STARMAP_FOR_VARIANT(variant, STARMAP_CALL)
+#undef STARMAP_CALL
+}
+#undef STARMAP_FOR_VARIANT
 }  // namespace
 
 int sweep_variant_count() { return kNumVariants; }
@@ -405,6 +523,27 @@ TileShape sweep_variant(int v) { return kVariants[v]; }
 size_t sweep_lds_bytes(int v, int slots, int storage) {
   const size_t s = storage == STORE_FP64 ? 8 : storage == STORE_FP32 ? 4 : 2;
   return size_t(slots) * (kVariants[v].tx + 1) * (kVariants[v].ty + 1) * s;
+}
+
+hipError_t prepare_sweep(int storage, int variant, int slots) {
+  if (variant < 0 || variant >= kNumVariants) return hipErrorInvalidValue;
+  switch (storage) {
+    case STORE_FP64: return prepare_typed<double>(variant, slots);
+    case STORE_FP32: return prepare_typed<float>(variant, slots);
+    case STORE_BF16: return prepare_typed<bf16>(variant, slots);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_batch(int storage, int variant, const BatchEntry* table, const int* first, int n_active,
+                              int items, int j, int slots, hipStream_t stream) {
+  if (variant < 0 || variant >= kNumVariants || n_active < 1 || items < 1) return hipErrorInvalidValue;
+  switch (storage) {
+    case STORE_FP64: return launch_batch_typed<double>(variant, table, first, n_active, items, j, slots, stream);
+    case STORE_FP32: return launch_batch_typed<float>(variant, table, first, n_active, items, j, slots, stream);
+    case STORE_BF16: return launch_batch_typed<bf16>(variant, table, first, n_active, items, j, slots, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep(int storage, int variant, const void* args, int slots, hipStream_t stream) {

@@ -197,6 +197,10 @@ class Solver:
     def run(self):
         B.check(B.lib().starmap_run(self._h))
 
+    def reset(self):
+        """Back to the initial condition at t = 0."""
+        B.check(B.lib().starmap_reset(self._h))
+
     def sweep(self, parity, tau, nsweeps=1):
         B.check(B.lib().starmap_sweep(self._h, int(parity), float(tau), int(nsweeps)))
 
@@ -262,6 +266,55 @@ class Solver:
             B.lib().starmap_destroy(self._h)
             self._h = ctypes.c_void_p()
         self._workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several solvers advanced together: one launch per sweep over all
+    instances still running, the whole run in one HIP graph.  The solvers must
+    outlive the batch (it keeps references to them)."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s._h.value for s in self.solvers])
+        self._h = ctypes.c_void_p()
+        B.check(B.lib().starmap_batch_create(arr, len(self.solvers), ctypes.byref(self._h)))
+
+    def run(self, use_graph=True):
+        """Advance every solver to t_final; returns the last_run record."""
+        B.check(B.lib().starmap_batch_run(self._h, 1 if use_graph else 0))
+        return self.last_run()
+
+    def last_run(self):
+        ms, up, by, nl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        B.check(B.lib().starmap_batch_last_run(self._h, ctypes.byref(ms), ctypes.byref(up), ctypes.byref(by),
+                                               ctypes.byref(nl)))
+        return {"ms": ms.value, "updates": up.value, "bytes": by.value, "launches": nl.value}
+
+    def reset(self):
+        for s in self.solvers:
+            s.reset()
+
+    def set_variant(self, variant, width):
+        B.check(B.lib().starmap_batch_set_variant(self._h, int(variant), int(width)))
+
+    def variant(self):
+        v, w = ctypes.c_int32(), ctypes.c_int32()
+        B.check(B.lib().starmap_batch_get_variant(self._h, ctypes.byref(v), ctypes.byref(w)))
+        return v.value, w.value
+
+    def autotune(self, sweeps=3):
+        B.check(B.lib().starmap_batch_autotune(self._h, int(sweeps)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            B.lib().starmap_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -1,0 +1,159 @@
+"""Batched heterogeneous solves on the GPU: one launch per sweep over all
+instances still running, the whole run in one HIP graph.  Every instance of a
+batch must equal its own single-instance run bit for bit (same tile, same
+programs, same arithmetic) and the oracle within the parity tolerance."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import paper_1211_2205_amd as pa
+import workloads as wl
+from gpu_helpers import rel_l2, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+P, X = wl.BC_PERIODIC, wl.BC_EXTRAPOLATION
+
+
+def _mixed(precision="fp64"):
+    """Orders 1..12, square and ragged grids, both boundary types, different
+    step counts (so the set of running instances shrinks during the run)."""
+    base = [
+        (11, 1, (20, 20), (X, X)),
+        (12, 3, (33, 29), (P, X)),
+        (13, 5, (47, 47), (X, X)),
+        (14, 9, (24, 24), (P, P)),
+        (15, 7, (70, 38), (X, P)),
+        (16, 12, (31, 31), (X, X)),
+        (17, 2, (65, 66), (X, X)),
+    ]
+    out = []
+    for seed, N, n, bc in base:
+        pr = wl.random_medium(seed, N, n[0], t_final=0.25, precision=precision)
+        out.append(dataclasses.replace(pr, n=n, bc=bc, name=f"{pr.name}_{n[0]}x{n[1]}"))
+    return out
+
+
+def _single(prob, variant, width, monkeypatch):
+    monkeypatch.setenv("STARMAP_CHUNK_WIDTH", str(width))
+    s = pa.Solver.from_problem(prob)
+    s.set_variant(variant)
+    s.run()
+    return s.moments()
+
+
+def _identical(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_batch_equals_single_runs_and_oracle(monkeypatch):
+    probs = _mixed()
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    steps = [s.nsteps for s in solvers]
+    assert len(set(steps)) > 3
+    b = pa.Batch(solvers)
+    print("batch", [p.name for p in probs], steps, flush=True)
+    rec = b.run(use_graph=True)
+    assert b.variant() == (0, 8)
+    assert rec["launches"] == 2 * max(steps) + 1
+    assert rec["updates"] == sum(s.nmom * p.n[0] * p.n[1] * n for s, p, n in zip(solvers, probs, steps))
+    for s in solvers:
+        assert s.time()[2] == s.nsteps
+    got = [s.moments() for s in solvers]
+    for p, g in zip(probs, got):
+        print("single", p.name, flush=True)
+        assert _identical(g, _single(p, 0, 8, monkeypatch)), p.name
+        o = run_oracle(p, fused=False)
+        err = rel_l2(g, o.u)
+        assert err < 1e-12, (p.name, err)
+    b.close()
+
+
+def test_batch_eager_graph_and_rerun_agree():
+    probs = _mixed()
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    b.run(use_graph=False)
+    eager = [s.moments() for s in solvers]
+    b.reset()
+    assert all(s.time()[2] == 0 for s in solvers)
+    b.run(use_graph=True)
+    g1 = [s.moments() for s in solvers]
+    b.reset()
+    b.run(use_graph=True)  # the captured graph is relaunched
+    g2 = [s.moments() for s in solvers]
+    for e, x, y in zip(eager, g1, g2):
+        assert _identical(e, x) and _identical(x, y)
+    # a finished batch has nothing left to run
+    rec = b.run()
+    assert rec["launches"] == 0 and rec["updates"] == 0
+    b.close()
+
+
+@pytest.mark.parametrize("variant,width", [(1, 4), (3, 6), (5, 4)])
+def test_batch_tile_variants(variant, width, monkeypatch):
+    probs = _mixed()
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    b.set_variant(variant, width)
+    b.run()
+    for p, s in zip(probs[:4], solvers[:4]):
+        assert _identical(s.moments(), _single(p, variant, width, monkeypatch)), (p.name, variant, width)
+    b.close()
+
+
+def test_batch_fp32_and_autotune(monkeypatch):
+    probs = _mixed("fp32")
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    b.autotune(2)
+    v, w = b.variant()
+    assert 0 <= v < 6 and w in (4, 6, 8)
+    b.run()
+    for p, s in zip(probs, solvers):
+        g = s.moments()
+        assert _identical(g, _single(p, v, w, monkeypatch)), p.name
+        err = rel_l2(g, run_oracle(p).u)
+        assert err < 1e-5, (p.name, err)
+    b.close()
+
+
+def test_batch_rejects_bad_input():
+    a = pa.Solver.from_problem(_mixed()[0])
+    c = pa.Solver.from_problem(_mixed("fp32")[1])
+    with pytest.raises(pa.StarmapError):
+        pa.Batch([a, c])  # mixed storage
+    with pytest.raises(pa.StarmapError):
+        pa.Batch([a, a])
+    with pytest.raises(pa.StarmapError):
+        pa.Batch([])
+    b = pa.Batch([a])
+    with pytest.raises(pa.StarmapError):
+        b.set_variant(0, 5)
+    with pytest.raises(pa.StarmapError):
+        b.set_variant(17, 8)
+    b.close()
+
+
+def test_c4_full_batch_sampled_instances(monkeypatch):
+    """The 256-instance FP32 batch at full size, in the launch configuration
+    the benchmark times: sampled instances equal their single runs bit for
+    bit, the smallest one matches the oracle, and all stay finite."""
+    probs = wl.batch(256, "fp32")
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    rec = b.run(use_graph=True)
+    print("c4", rec, flush=True)
+    steps = [s.nsteps for s in solvers]
+    sizes = [p.n[0] for p in probs]
+    pick = sorted({int(np.argmin(steps)), int(np.argmax(steps)), int(np.argmax([p.N for p in probs]))})
+    for i in pick:
+        assert _identical(solvers[i].moments(), _single(probs[i], 0, 8, monkeypatch)), probs[i].name
+    i = int(np.argmin(sizes))
+    err = rel_l2(solvers[i].moments(), run_oracle(probs[i]).u)
+    assert err < 1e-5, (probs[i].name, err)
+    for s in solvers:
+        d = s.diagnostics()
+        assert d["nonfinite"] == 0 and d["maxabs"] > 0
+    b.close()
