@@ -10,5 +10,8 @@ the two share no code.  Modules:
   scheme  the half-step operators and the time loop (Sects. 4-5), driving a
           plain C implementation (starmap_oracle.c) of the differences and the
           exact sub-step update
-  mlp     the learned-closure network: forward, hand-written backward, Adam
+  mlp     the learned-closure network: forward, hand-written backward, Adam,
+          optional bfloat16 rounding of the matrix-product operands
+  closure the learned closure of P_5: input features, order-6 flux targets,
+          closure terms and the closure solver
 """
