@@ -231,6 +231,78 @@ int starmap_sweep_bytes(const starmap_solver* s, int32_t parity, double* bytes);
 int starmap_profile_begin(starmap_solver* s);
 int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches, double* bytes);
 
+/* ----------------------------------------------------------- learned closure */
+
+/* The P_N truncation closes the hierarchy by zeroing order N + 1 (Sect. 2).
+   A solver created with closure = STARMAP_CLOSURE_LEARNED (N = 5 only)
+   restores an estimate of the dropped order-6 flux of its six order-5 moments
+   with a small network of the local order-4/5 data, evaluated on the device
+   before every odd sweep and added to those moments' residual W_k:
+     - evaluation points (i, j), 0 <= i <= nx, 0 <= j <= ny; the order-5 R
+       moments (grid G21) take the outputs at their point (i, j), the I
+       moments (G12) at theirs, where those points exist;
+     - inputs (128): for each of R_4^4, I_4^4, R_4^2, I_4^2, R_4^0, R_5^5,
+       I_5^5, R_5^3, I_5^3, R_5^1, I_5^1 the values at the array neighbours
+       (i + a, j + b), b = -1..1 (outer), a = -1..1 (inner), clamped to that
+       moment's array, divided by nu = sqrt(sum of their squares) + 1e-20;
+       then log10(sigma_a + 0.01) and log10(sigma_s + 0.01) at the G11 cell
+       (min(i, nx-1), min(j, ny-1)); then zeros;
+     - network y = W3 gelu(W2 gelu(W1 x + b1) + b2) + b3 (128, 128, 6 units,
+       exact-erf GELU), matrix-product operands rounded to bfloat16, FP32
+       accumulation;
+     - closure term of output r (R_5^5, I_5^5, R_5^3, I_5^3, R_5^1, I_5^1):
+       g_r = nu * y_r / dx.
+   The term is evaluated on the state at the start of each odd sweep and held
+   fixed during it (like W).  Closure solvers need isotropic scattering,
+   time-independent data and no source on the order-5 moments.
+
+   Parameter blob (FP32, STARMAP_CLOSURE_PARAMS values, row-major):
+   W1 (128 x 128, out x in), b1 (128), W2 (128 x 128), b2 (128), W3 (6 x 128),
+   b3 (6). */
+#define STARMAP_CLOSURE_PARAMS 33798
+
+/* Copy the network into the solver (converted to its device form).  Must
+   precede the first advance of a closure solver. */
+int starmap_closure_load(starmap_solver* s, const float* weights, size_t count);
+
+/* Training samples from the current state of a solver of order N >= 6
+   (isotropic scattering): for count cells points[2 i], points[2 i + 1] =
+   (i, j) with 0 <= i < nx, 0 <= j < ny, writes the closure inputs
+   (count x 128, FP32) to the device array features and the targets
+   F_r dx / nu (count x 6, FP32) to the device array targets, where
+   F_r = -sum over order-6 moments j of (Mx(k_r, j) D_x u_j + My(k_r, j) D_y u_j)
+   at output r's point (i, j) is the flux the truncation to P_5 drops.  Both
+   arrays are caller-owned device memory; the call synchronises. */
+int starmap_closure_samples(starmap_solver* s, const int32_t* points, int32_t count, float* features,
+                            float* targets);
+
+/* Network trainer on the device: parameters (FP32 master copy), Adam state,
+   and buffers for batches of up to max_batch samples; work runs on
+   hip_stream (NULL: the null stream).  x (batch x 128) and t (batch x 6) are
+   device arrays.  Loss = mean over the batch and the six outputs of
+   (y - t)^2.  The matrix products (forward and backward) use bfloat16
+   operands with FP32 accumulation; the backward pass rounds dY, dZ2 and dZ1
+   to bfloat16 where they enter a product; biases' gradients sum the
+   unrounded values. */
+typedef struct starmap_mlp starmap_mlp;
+int starmap_mlp_create(int32_t max_batch, void* hip_stream, starmap_mlp** out);
+void starmap_mlp_destroy(starmap_mlp* n);
+/* Set (and reset the Adam state) / read the parameter blob (host memory). */
+int starmap_mlp_set_params(starmap_mlp* n, const float* params, size_t count);
+int starmap_mlp_get_params(const starmap_mlp* n, float* params, size_t count);
+/* y (batch x 6, device) = network(x).  Asynchronous. */
+int starmap_mlp_forward(starmap_mlp* n, const float* x, int32_t batch, float* y);
+/* Gradient of the loss (parameter-blob layout, host memory; may be NULL) and
+   the loss (may be NULL); synchronises. */
+int starmap_mlp_gradients(starmap_mlp* n, const float* x, const float* t, int32_t batch, float* grad_host,
+                          double* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+   batch's gradient.  loss may be NULL (then the call does not synchronise). */
+int starmap_mlp_train_step(starmap_mlp* n, const float* x, const float* t, int32_t batch, double lr,
+                           double* loss);
+/* One Adam step with a given gradient (host memory); synchronises. */
+int starmap_mlp_adam_step(starmap_mlp* n, const float* grad_host, double lr);
+
 /* Restore the initial condition at t = 0 (step 0) on the device. */
 int starmap_reset(starmap_solver* s);
 

@@ -18,6 +18,7 @@ EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = -1, -2, -3, -4, -5
 BC_PERIODIC, BC_EXTRAPOLATION = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
 CLOSURE_PN, CLOSURE_LEARNED = 0, 1
+CLOSURE_PARAMS = 33798
 FIELD_ABSORPTION, FIELD_SCATTERING, FIELD_SOURCE, FIELD_INITIAL = 0, 1, 2, 3
 
 _ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EUNSTABLE: "EUNSTABLE", ESTATE: "ESTATE"}
@@ -44,6 +45,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _szp = ctypes.POINTER(ctypes.c_size_t)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 # (name, argtypes, restype)
 SIGNATURES = [
@@ -79,6 +81,16 @@ SIGNATURES = [
     ("starmap_sweep_bytes", [_vp, ctypes.c_int32, _dp], ctypes.c_int),
     ("starmap_profile_begin", [_vp], ctypes.c_int),
     ("starmap_profile_end", [_vp, _dp, _i64p, _dp], ctypes.c_int),
+    ("starmap_closure_load", [_vp, _fp, ctypes.c_size_t], ctypes.c_int),
+    ("starmap_closure_samples", [_vp, _i32p, ctypes.c_int32, _vp, _vp], ctypes.c_int),
+    ("starmap_mlp_create", [ctypes.c_int32, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    ("starmap_mlp_destroy", [_vp], None),
+    ("starmap_mlp_set_params", [_vp, _fp, ctypes.c_size_t], ctypes.c_int),
+    ("starmap_mlp_get_params", [_vp, _fp, ctypes.c_size_t], ctypes.c_int),
+    ("starmap_mlp_forward", [_vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
+    ("starmap_mlp_gradients", [_vp, _vp, _vp, ctypes.c_int32, _fp, _dp], ctypes.c_int),
+    ("starmap_mlp_train_step", [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, _dp], ctypes.c_int),
+    ("starmap_mlp_adam_step", [_vp, _fp, ctypes.c_double], ctypes.c_int),
     ("starmap_reset", [_vp], ctypes.c_int),
     ("starmap_batch_create", [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp)], ctypes.c_int),
     ("starmap_batch_destroy", [_vp], None),

@@ -18,10 +18,12 @@
 #include "../../include/starmap.h"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "solver.hpp"
 
 using namespace starmap;
 
-namespace {
+namespace starmap {
+namespace detail {
 
 thread_local std::string g_last_error;
 
@@ -30,89 +32,13 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t _e = (expr);                                                             \
-    if (_e != hipSuccess)                                                               \
-      return fail(STARMAP_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
-  } while (0)
+}  // namespace detail
+}  // namespace starmap
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+using namespace starmap::detail;
 
-struct FieldSource {
-  starmap_field_fn fn = nullptr;
-  void* ctx = nullptr;
-  bool time_dependent = false;
-  // pre-sampled values on grid g = (gx-1) + 2 (gy-1), public layout
-  std::array<std::vector<double>, 4> arrays;
-  bool has_array[4] = {false, false, false, false};
-  bool set() const { return fn || has_array[0] || has_array[1] || has_array[2] || has_array[3]; }
-};
-
-int grid_id(int gx, int gy) { return (gx - 1) + 2 * (gy - 1); }
-
-}  // namespace
-
-struct starmap_solver {
-  starmap_problem prob{};
-  int N = 0, nmom = 0;
-  std::vector<MomentInfo> moms;
-  std::vector<CouplingRow> rows;
-  double rho = 0, dx = 0, dy = 0, dt = 0;
-  int64_t steps_total = 0, steps_done = 0;
-  double t = 0;
-  int nx = 0, ny = 0, px = 0, py = 0;
-  int storage = STORE_FP64;
-  size_t ssize = 8, csize = 8;
-  int pitch = 0, nrows = 0;
-  int64_t plane_stride = 0;
-
-  FieldSource absorption, scattering;
-  std::map<int, FieldSource> scattering_order;  // l -> sigma_sl
-  std::map<int, FieldSource> source;            // k -> q_k
-  std::map<int, FieldSource> initial;           // k -> u_k(0)
-  bool anisotropic = false;
-  bool time_dependent = false;
-
-  DecayMap dmap;
-  std::vector<int32_t> qk;  // per moment: source plane or -1
-  int nsrc = 0;
-
-  // device
-  void* dev = nullptr;
-  size_t dev_bytes = 0;
-  bool owns_dev = false;
-  bool owns_stream = false;
-  hipStream_t stream = nullptr;
-  bool bound = false;
-  size_t off_state = 0, off_decay = 0, off_src = 0, off_prog[2] = {0, 0}, off_diag = 0;
-  size_t prog_bytes[2] = {0, 0};
-  int diag_rows_per_block = 64, diag_nblocks = 0;
-
-  bool device_ready = false;     // workspace allocated and state uploaded
-  bool materials_ready = false;  // decay and source planes uploaded for current time
-  int variant = -1;              // -1: not chosen yet
-  int slots = 0;
-  int nchunks = 1;               // m ranges per tile (workgroups per tile and sweep)
-  int chunk_width = 0;           // m indices per range (0: default)
-  SweepProgram prog[2];
-  bool prog_uploaded = false;
-
-  // per-launch HIP events of the sweep kernel (starmap_profile_begin/end)
-  bool profiling = false;
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-  double prof_bytes = 0.0;
-  double sweep_bytes_cache[2] = {-1.0, -1.0};
-
-  // plane_stride is a multiple of 128 elements, so planes of every element
-  // size start 256-byte aligned and state and material planes share one
-  // element stride
-  size_t plane_bytes_state() const { return size_t(plane_stride) * ssize; }
-  size_t plane_bytes_c() const { return size_t(plane_stride) * csize; }
-};
-
-namespace {
+namespace starmap {
+namespace detail {
 
 int points_x(const starmap_solver* s, int gx) { return gx == AXIS_CELL ? s->nx : s->nx + 1 - s->px; }
 int points_y(const starmap_solver* s, int gy) { return gy == AXIS_CELL ? s->ny : s->ny + 1 - s->py; }
@@ -241,6 +167,10 @@ void layout(starmap_solver* s) {
   s->nsrc = 0;
   for (auto& kv : s->source)
     if (kv.second.set()) s->qk[kv.first] = s->nsrc++;
+  // a closure solver adds its terms to the order-N rows through source planes
+  if (s->closure)
+    for (int k = 0; k < s->nmom; ++k)
+      if (s->moms[k].l == s->N) s->qk[k] = s->nsrc++;
   // m ranges of a few indices keep a window within the register and LDS budget
   // of the compiled tiles.  The width is tuned; the program region is sized
   // for the narrowest candidate (most ranges), and program sizes do not depend
@@ -277,6 +207,10 @@ void layout(starmap_solver* s) {
   int max_rows = s->ny + 1;
   s->diag_nblocks = diag_blocks(s->nmom, max_rows, s->diag_rows_per_block);
   off += align256(size_t(s->diag_nblocks) * 4 * 8) + 256 + align256(size_t(s->nmom) * 8);
+  if (s->closure) {
+    s->off_net = off;
+    off += align256(sizeof(ClosureNet));
+  }
   s->dev_bytes = off;
 }
 
@@ -503,7 +437,11 @@ int launch_one(starmap_solver* s, int parity, double tau) {
 
 double sweep_bytes_of(const starmap_solver* s, int parity);
 
-int sweep(starmap_solver* s, int parity, double tau) {
+int sweep(starmap_solver* s, int parity, double tau, bool with_closure = true) {
+  if (parity == 1 && s->closure && with_closure) {
+    int rc = closure_before_odd(s);
+    if (rc) return rc;
+  }
   if (s->profiling) {
     if (s->ev_used + 2 > s->ev.size()) {
       for (int i = 0; i < 64; ++i) {
@@ -558,7 +496,8 @@ int set_field(starmap_solver* s, FieldSource& f, starmap_field_fn fn, void* ctx,
   return STARMAP_OK;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace starmap
 
 // ===================================================================== ABI
 extern "C" {
@@ -635,6 +574,8 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out) {
   if (!s) return fail(STARMAP_ENOMEM, "out of host memory");
   s->prob = *prob;
   s->N = prob->N;
+  s->closure = prob->closure == STARMAP_CLOSURE_LEARNED;
+  if (s->closure && s->N != 5) return fail(STARMAP_EINVAL, "the learned closure is defined for N = 5");
   s->nmom = moment_count(s->N);
   try {
     s->moms = moment_list(s->N);
@@ -664,6 +605,8 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out) {
 
 void starmap_destroy(starmap_solver* s) {
   if (!s) return;
+  if (s->device_ready) (void)hipStreamSynchronize(s->stream);
+  if (s->sample_buf) (void)hipFree(s->sample_buf);
   if (s->owns_dev && s->dev) (void)hipFree(s->dev);
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -696,6 +639,8 @@ int starmap_set_source(starmap_solver* s, int32_t k, starmap_field_fn f, void* c
   if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
   int rc = check_k(s, k);
   if (rc) return rc;
+  if (s->closure && s->moms[k].l == s->N)
+    return fail(STARMAP_EINVAL, "a closure solver carries its own terms on the order-N moments; no source there");
   const bool is_new = s->source.find(k) == s->source.end() || !s->source[k].set();
   if (s->device_ready && is_new) return fail(STARMAP_ESTATE, "new source moments must be set before the first device call");
   rc = set_field(s, s->source[k], f, ctx, td);
@@ -726,6 +671,8 @@ int starmap_set_field_array(starmap_solver* s, int32_t which, int32_t k, const d
     case STARMAP_FIELD_ABSORPTION: f = &s->absorption; break;
     case STARMAP_FIELD_SCATTERING: f = &s->scattering; break;
     case STARMAP_FIELD_SOURCE: {
+      if (s->closure && s->moms[k].l == s->N)
+        return fail(STARMAP_EINVAL, "a closure solver carries its own terms on the order-N moments; no source there");
       const bool is_new = s->source.find(k) == s->source.end() || !s->source[k].set();
       if (s->device_ready && is_new) return fail(STARMAP_ESTATE, "new source moments must be set before the first device call");
       f = &s->source[k];
@@ -790,6 +737,7 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
   if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
   if (nsteps < 0) return fail(STARMAP_EINVAL, "negative step count");
   if (nsteps == 0) return STARMAP_OK;
+  if (s->closure && s->time_dependent) return fail(STARMAP_EINVAL, "the learned closure needs time-independent data");
   int rc = ensure_device(s);
   if (rc) return rc;
   const double dt = s->dt;
@@ -1021,13 +969,13 @@ int starmap_autotune(starmap_solver* s, int32_t sweeps) {
       if (sweep_lds_bytes(v, s->slots, s->storage) > size_t(max_lds)) continue;
       // tau = 0 leaves every value unchanged (u + 0 * r = u), so timing on the
       // live state is harmless
-      rc = sweep(s, 0, 0.0);
-      if (!rc) rc = sweep(s, 1, 0.0);
+      rc = sweep(s, 0, 0.0, false);
+      if (!rc) rc = sweep(s, 1, 0.0, false);
       if (rc) break;
       HIP_TRY(hipEventRecord(e0, s->stream));
       for (int i = 0; i < sweeps && !rc; ++i) {
-        rc = sweep(s, 0, 0.0);
-        if (!rc) rc = sweep(s, 1, 0.0);
+        rc = sweep(s, 0, 0.0, false);
+        if (!rc) rc = sweep(s, 1, 0.0, false);
       }
       if (rc) break;
       HIP_TRY(hipEventRecord(e1, s->stream));
@@ -1102,7 +1050,8 @@ int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches,
 
 }  // extern "C"
 
-namespace {
+namespace starmap {
+namespace detail {
 
 double sweep_bytes_of(const starmap_solver* s, int parity) {
   double b = 0.0;
@@ -1129,7 +1078,8 @@ double sweep_bytes_of(const starmap_solver* s, int parity) {
   return b;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace starmap
 
 extern "C" const char* starmap_last_error(void) { return g_last_error.c_str(); }
 
@@ -1172,7 +1122,8 @@ struct starmap_batch {
   int64_t last_updates = 0, last_launches = 0;
 };
 
-namespace {
+namespace starmap {
+namespace detail {
 
 size_t batch_table_bytes(int count) { return align256(size_t(count) * sizeof(BatchEntry)) + size_t(count + 1) * 4; }
 
@@ -1322,7 +1273,8 @@ int batch_sync_solvers(starmap_batch* b) {
   return STARMAP_OK;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace starmap
 
 extern "C" {
 
@@ -1334,6 +1286,7 @@ int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_
   for (int i = 0; i < count; ++i) {
     if (!v[i]) return fail(STARMAP_EINVAL, "NULL solver in batch");
     if (v[i]->time_dependent) return fail(STARMAP_EINVAL, "batched solvers need time-independent data");
+    if (v[i]->closure) return fail(STARMAP_EINVAL, "closure solvers are not batched");
     if (v[i]->storage != v[0]->storage) return fail(STARMAP_EINVAL, "batched solvers need one storage precision");
   }
   {

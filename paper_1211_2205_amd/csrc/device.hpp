@@ -1,0 +1,66 @@
+// Device helpers shared by the kernels of the library: storage types, the
+// compute type of each, bfloat16 rounding, boundary index maps and the
+// XCD-aware block order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace starmap {
+
+struct bf16 {
+  uint16_t bits;
+};
+
+template <typename T> struct ComputeOf { using type = float; };
+template <> struct ComputeOf<double> { using type = double; };
+
+__device__ __forceinline__ double to_c(double v) { return v; }
+__device__ __forceinline__ float to_c(float v) { return v; }
+__device__ __forceinline__ float to_c(bf16 v) { return __uint_as_float(uint32_t(v.bits) << 16); }
+
+template <typename T> __device__ __forceinline__ T from_c(typename ComputeOf<T>::type v);
+template <> __device__ __forceinline__ double from_c<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_c<float>(float v) { return v; }
+template <> __device__ __forceinline__ bf16 from_c<bf16>(float v) {
+  // round to nearest even; NaN stays NaN
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return bf16{uint16_t((u >> 16) | 0x40u)};
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return bf16{uint16_t(u >> 16)};
+}
+
+__device__ __forceinline__ double expm1_c(double z) { return expm1(z); }
+__device__ __forceinline__ float expm1_c(float z) { return expm1f(z); }
+
+// E(z) = (e^z - 1) / z with E(0) = 1.
+template <typename C>
+__device__ __forceinline__ C expm1div(C z) {
+  return z == C(0) ? C(1) : expm1_c(z) / z;
+}
+
+// Index of an LDS staging load along one axis: periodic grids wrap, the others
+// clamp to the last stored point (the constant-extrapolation ghosts of cell
+// grids are exactly the clamped neighbours; clamped nodal points beyond the
+// grid only feed outputs that are not stored).
+__device__ __forceinline__ int map_axis(int i, int n, int periodic, int is_cell) {
+  if (periodic) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  const int last = is_cell ? n - 1 : n;
+  return i < 0 ? 0 : (i > last ? last : i);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; hand each XCD a
+// contiguous range of tiles so the halos of neighbouring tiles hit its L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int q = nblocks / 8, r = nblocks % 8;
+  const int xcd = b % 8, idx = b / 8;
+  // XCD x owns tiles [start(x), start(x) + q + (x < r))
+  const int start = xcd * q + (xcd < r ? xcd : r);
+  return start + idx;
+}
+
+}  // namespace starmap

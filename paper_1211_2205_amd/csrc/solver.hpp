@@ -1,0 +1,130 @@
+// Private interface of the library's host side: the solver object and the
+// helpers shared by the C-ABI sources (capi.cpp, closure.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/starmap.h"
+#include "kernels.hpp"
+#include "mlp.hpp"
+#include "plan.hpp"
+
+namespace starmap {
+namespace detail {
+
+// Records msg as the calling thread's last error and returns code.
+int fail(int code, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(STARMAP_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct FieldSource {
+  starmap_field_fn fn = nullptr;
+  void* ctx = nullptr;
+  bool time_dependent = false;
+  // pre-sampled values on grid g = (gx-1) + 2 (gy-1), public layout
+  std::array<std::vector<double>, 4> arrays;
+  bool has_array[4] = {false, false, false, false};
+  bool set() const { return fn || has_array[0] || has_array[1] || has_array[2] || has_array[3]; }
+};
+
+inline int grid_id(int gx, int gy) { return (gx - 1) + 2 * (gy - 1); }
+
+}  // namespace detail
+}  // namespace starmap
+
+struct starmap_solver {
+  starmap_problem prob{};
+  int N = 0, nmom = 0;
+  std::vector<starmap::MomentInfo> moms;
+  std::vector<starmap::CouplingRow> rows;
+  double rho = 0, dx = 0, dy = 0, dt = 0;
+  int64_t steps_total = 0, steps_done = 0;
+  double t = 0;
+  int nx = 0, ny = 0, px = 0, py = 0;
+  int storage = starmap::STORE_FP64;
+  size_t ssize = 8, csize = 8;
+  int pitch = 0, nrows = 0;
+  int64_t plane_stride = 0;
+
+  starmap::detail::FieldSource absorption, scattering;
+  std::map<int, starmap::detail::FieldSource> scattering_order;  // l -> sigma_sl
+  std::map<int, starmap::detail::FieldSource> source;            // k -> q_k
+  std::map<int, starmap::detail::FieldSource> initial;           // k -> u_k(0)
+  bool anisotropic = false;
+  bool time_dependent = false;
+
+  starmap::DecayMap dmap;
+  std::vector<int32_t> qk;  // per moment: source plane or -1
+  int nsrc = 0;
+
+  // device
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  bool owns_dev = false;
+  bool owns_stream = false;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  size_t off_state = 0, off_decay = 0, off_src = 0, off_prog[2] = {0, 0}, off_diag = 0;
+  size_t prog_bytes[2] = {0, 0};
+  int diag_rows_per_block = 64, diag_nblocks = 0;
+
+  bool device_ready = false;     // workspace allocated and state uploaded
+  bool materials_ready = false;  // decay and source planes uploaded for current time
+  int variant = -1;              // -1: not chosen yet
+  int slots = 0;
+  int nchunks = 1;               // m ranges per tile (workgroups per tile and sweep)
+  int chunk_width = 0;           // m indices per range (0: default)
+  starmap::SweepProgram prog[2];
+  bool prog_uploaded = false;
+
+  // per-launch HIP events of the sweep kernel (starmap_profile_begin/end)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double prof_bytes = 0.0;
+  double sweep_bytes_cache[2] = {-1.0, -1.0};
+
+  // learned closure (order 5): network region, geometry, weights loaded
+  bool closure = false;
+  bool closure_loaded = false;
+  size_t off_net = 0;
+  starmap::ClosureGeo cgeo{};
+  void* sample_buf = nullptr;  // device copy of training-sample points
+  size_t sample_cap = 0;
+
+  // plane_stride is a multiple of 128 elements, so planes of every element
+  // size start 256-byte aligned and state and material planes share one
+  // element stride
+  size_t plane_bytes_state() const { return size_t(plane_stride) * ssize; }
+  size_t plane_bytes_c() const { return size_t(plane_stride) * csize; }
+};
+
+namespace starmap {
+namespace detail {
+
+int points_x(const starmap_solver* s, int gx);
+int points_y(const starmap_solver* s, int gy);
+char* dptr(const starmap_solver* s, size_t off);
+int ensure_device(starmap_solver* s);
+int upload_materials(starmap_solver* s, double t_eval);
+
+// Closure (closure.cpp): geometry of a solver's closure inputs, and the
+// fused closure kernel run before every odd sweep of a closure solver.
+int closure_geometry(const starmap_solver* s, ClosureGeo* g, bool with_terms);
+int closure_before_odd(starmap_solver* s);
+
+}  // namespace detail
+}  // namespace starmap

@@ -102,12 +102,12 @@ class Solver:
         self._workspace = None
 
     @classmethod
-    def from_problem(cls, prob, device=None, precision=None):
+    def from_problem(cls, prob, device=None, precision=None, closure="pn"):
         """Build from a problem description object with the attributes
         N, n, ax, bc, cfl, t_final, sigma_a, sigma_s0, sigma_sl, source,
         initial, time_dependent, precision (fields are f(t, x, y))."""
         s = cls(prob.N, prob.n, prob.ax, prob.bc, prob.cfl, prob.t_final,
-                precision or prob.precision, device=device)
+                precision or prob.precision, device=device, closure=closure)
         td = int(bool(getattr(prob, "time_dependent", False)))
         s.set_absorption(prob.sigma_a, td)
         s.set_scattering(prob.sigma_s0, td)
@@ -196,6 +196,25 @@ class Solver:
 
     def run(self):
         B.check(B.lib().starmap_run(self._h))
+
+    def load_closure(self, params):
+        """Load the closure network (flat FP32 parameter blob, see
+        include/starmap.h) into a solver created with closure="learned"."""
+        w = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        B.check(B.lib().starmap_closure_load(self._h, w.ctypes.data_as(B._fp), w.size))
+
+    def closure_samples(self, points, features, targets):
+        """Closure inputs and order-6 flux targets at cells points[r] = (i, j)
+        of this (order >= 6) solver's current state, written into the float32
+        device tensors features (count x 128) and targets (count x 6)."""
+        pts = np.ascontiguousarray(points, dtype=np.int32).reshape(-1, 2)
+        n = pts.shape[0]
+        assert features.is_cuda and targets.is_cuda and features.is_contiguous() and targets.is_contiguous()
+        assert features.dtype == targets.dtype and str(features.dtype) == "torch.float32"
+        assert features.numel() >= n * 128 and targets.numel() >= n * 6
+        B.check(B.lib().starmap_closure_samples(self._h, pts.ctypes.data_as(B._i32p), n,
+                                                ctypes.c_void_p(features.data_ptr()),
+                                                ctypes.c_void_p(targets.data_ptr())))
 
     def reset(self):
         """Back to the initial condition at t = 0."""
@@ -314,6 +333,69 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             B.lib().starmap_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The closure network's trainer on the device (forward, backward and Adam
+    in the library's kernels).  Batches are float32 torch device tensors;
+    work runs on torch's current stream."""
+
+    def __init__(self, max_batch, device=None):
+        import torch
+        dev = torch.device(device or "cuda")
+        self._stream = torch.cuda.current_stream(dev)
+        self._h = ctypes.c_void_p()
+        B.check(B.lib().starmap_mlp_create(int(max_batch), ctypes.c_void_p(self._stream.cuda_stream),
+                                           ctypes.byref(self._h)))
+        self.max_batch = int(max_batch)
+
+    @staticmethod
+    def _dev(t, cols):
+        assert t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float32" and t.shape[-1] == cols
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_params(self, params):
+        w = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        B.check(B.lib().starmap_mlp_set_params(self._h, w.ctypes.data_as(B._fp), w.size))
+
+    def params(self):
+        w = np.empty(B.CLOSURE_PARAMS, dtype=np.float32)
+        B.check(B.lib().starmap_mlp_get_params(self._h, w.ctypes.data_as(B._fp), w.size))
+        return w
+
+    def forward(self, x):
+        import torch
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
+        B.check(B.lib().starmap_mlp_forward(self._h, self._dev(x, 128), x.shape[0], self._dev(y, 6)))
+        return y
+
+    def gradients(self, x, t):
+        g = np.empty(B.CLOSURE_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        B.check(B.lib().starmap_mlp_gradients(self._h, self._dev(x, 128), self._dev(t, 6), x.shape[0],
+                                              g.ctypes.data_as(B._fp), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, t, lr, want_loss=False):
+        loss = ctypes.c_double()
+        B.check(B.lib().starmap_mlp_train_step(self._h, self._dev(x, 128), self._dev(t, 6), x.shape[0], float(lr),
+                                               ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def adam_step(self, grad, lr):
+        g = np.ascontiguousarray(grad, dtype=np.float32).ravel()
+        B.check(B.lib().starmap_mlp_adam_step(self._h, g.ctypes.data_as(B._fp), float(lr)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            B.lib().starmap_mlp_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
