@@ -527,9 +527,18 @@ hipError_t launch_infer_t(void* U, const void* decay, const ClosureGeo& G, const
 
 hipError_t launch_closure_infer(int storage, void* U, const void* decay, const ClosureGeo& G, const ClosureNet* net,
                                 hipStream_t stream) {
+  // one workgroup per compute unit (the network fills most of its LDS), each
+  // looping over blocks of points with the weights loaded once
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+  }
   const int total = (G.nx + 1) * (G.ny + 1);
   const int nblk = (total + CB - 1) / CB;
-  const int blocks = std::min(nblk, 1024);
+  const int blocks = std::min(nblk, cus);
   switch (storage) {
     case STORE_FP64: return launch_infer_t<double>(U, decay, G, net, blocks, stream);
     case STORE_FP32: return launch_infer_t<float>(U, decay, G, net, blocks, stream);

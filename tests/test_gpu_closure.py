@@ -213,3 +213,28 @@ def test_closure_errors():
         r.load_closure(mlp.flatten(_params(1)))  # not a closure solver
     with pytest.raises(pa.StarmapError):
         pa.Batch([s])
+
+
+def test_trained_closure_gains_over_plain_p5():
+    """The committed network, on held-out instances (closure seeds 2000..2003,
+    never seen in training or calibration): the P_5 + closure zeroth moment is
+    closer to the P_31 solution than plain P_5's on every instance."""
+    import os
+    w = np.load(os.path.join(os.path.dirname(pa.__file__), "weights", "closure_p5_256.npy"), allow_pickle=False)
+    assert w.shape == (33798,) and w.dtype == np.float32
+    gains = []
+    for k in range(2000, 2004):
+        runs = {}
+        for label, N, cl in (("ref", 31, None), ("p5", 5, None), ("p5c", 5, w)):
+            s = pa.Solver.from_problem(wl.closure_instance(k, N, 256), precision="fp32",
+                                       closure="learned" if cl is not None else "pn")
+            if cl is not None:
+                s.load_closure(cl)
+            s.run()
+            runs[label] = s.get_moment(0)
+            s.close()
+        e5 = oc.r00_error(runs["p5"], runs["ref"])
+        ec = oc.r00_error(runs["p5c"], runs["ref"])
+        print(f"held-out {k}: P_5 error {e5:.3e}, P_5 + closure {ec:.3e}", flush=True)
+        gains.append(e5 / ec)
+    assert min(gains) > 1.2, gains
