@@ -40,6 +40,13 @@ __device__ __forceinline__ uint32_t bf16_bits(double v) {
 
 __device__ __forceinline__ float bf16_value(uint32_t bits) { return __uint_as_float(bits << 16); }
 
+// The same rounding (nearest, ties to even) by the conversion instruction.
+__device__ __forceinline__ uint32_t bf16_hw(float v) {
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
+}
+__device__ __forceinline__ uint32_t bf16_in(float v) { return bf16_hw(v); }
+__device__ __forceinline__ uint32_t bf16_in(double v) { return bf16_bits(v); }
+
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
@@ -296,42 +303,60 @@ __global__ void __launch_bounds__(256) closure_samples_kernel(const T* __restric
 }
 
 // ------------------------------------------------------------ fused closure
-// Every workgroup holds the network in LDS and loops over blocks of 64
-// evaluation points of the (nx + 1) x (ny + 1) index domain: gather and
-// normalise the inputs, three MFMA layers (waves split the 128 hidden units;
-// the last layer gives each wave 16 points), then nu * y / dx into the
-// closure planes of the order-5 moments.
+// Every workgroup keeps the network and loops over blocks of 64 evaluation
+// points of the (nx + 1) x (ny + 1) index domain: gather and normalise the
+// inputs, three MFMA layers, then nu * y / dx into the closure planes of the
+// order-5 moments.  The layers are computed transposed, H^T = W X^T: the
+// weights are the A operand and stay in registers (wave w owns hidden units
+// [32 w, 32 w + 32)), the activations are the B operand, read from LDS as
+// [point][unit] rows, and each lane's four outputs (consecutive units of one
+// point) go back with one 8-byte LDS write.
 constexpr int CB = 64;               // evaluation points per block
-constexpr int LDW = CLOSURE_IN + 8;  // LDS row of weights and activations (bf16)
+constexpr int LDW = CLOSURE_IN + 8;  // LDS row of one point's activations (bf16), padded
+
+// GELU with erf from Abramowitz & Stegun, Handbook of Mathematical Functions,
+// formula 7.1.26 (|error| <= 1.5e-7 on the real line).
+__device__ __forceinline__ float gelu_fast(float z) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  const float erf_abs = 1.0f - poly * __expf(-x * x);
+  return 0.5f * z * (1.0f + copysignf(erf_abs, z));
+}
 
 template <typename T>
-__global__ void __launch_bounds__(256) closure_infer_kernel(T* __restrict__ U,
+__global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U,
                                                             const typename ComputeOf<T>::type* __restrict__ decay,
                                                             const ClosureGeo G, const ClosureNet* __restrict__ net) {
   using C = typename ComputeOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  uint16_t* W1 = reinterpret_cast<uint16_t*>(smem);  // [128][LDW]
-  uint16_t* W2 = W1 + CLOSURE_HIDDEN * LDW;          // [128][LDW]
-  uint16_t* W3 = W2 + CLOSURE_HIDDEN * LDW;          // [16][LDW], rows >= 6 zero
-  uint16_t* Xa = W3 + 16 * LDW;                      // [64][LDW] inputs, then layer-2 activations
+  uint16_t* Xa = reinterpret_cast<uint16_t*>(smem);  // [64][LDW] inputs, then layer-2 activations
   uint16_t* Xb = Xa + CB * LDW;                      // [64][LDW] layer-1 activations
-  C* nu_s = reinterpret_cast<C*>(Xb + CB * LDW);  // [64]
-  C* part = nu_s + CB;                            // [4][64] partial sums of squares per wave
+  uint16_t* W3 = Xb + CB * LDW;                      // [16][LDW] output layer, rows >= 6 zero
+  C* nu_s = reinterpret_cast<C*>(W3 + 16 * LDW);     // [64]
+  C* part = nu_s + CB;                                    // [4][64] partial sums of squares per wave
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int fk = 8 * (lane >> 4);
 
-  // weights: bf16 rows of 128, copied 16 bytes at a time
-  for (int e = tid; e < (2 * CLOSURE_HIDDEN + 16) * (CLOSURE_IN / 8); e += 256) {
-    const int row = e / (CLOSURE_IN / 8), c8 = (e % (CLOSURE_IN / 8)) * 8;
-    const uint4 v = reinterpret_cast<const uint4*>(net->w)[e];
-    *reinterpret_cast<uint4*>(&W1[row * LDW + c8]) = v;  // W1, W2, W3 rows are consecutive
-  }
-  float b1[2], b2[2];
+  // this wave's weight fragments: rows 32 w + 16 mi + (lane % 16), k = 32 ks + fk
+  const uint4* wv = reinterpret_cast<const uint4*>(net->w);  // rows of CLOSURE_IN / 8 uint4
+  uint4 wf[2][2][4];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    b1[j] = net->b1[32 * w + 16 * j + (lane & 15)];
-    b2[j] = net->b2[32 * w + 16 * j + (lane & 15)];
-  }
-  const float b3 = net->b3[lane & 15];
+  for (int layer = 0; layer < 2; ++layer)
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int row = layer * CLOSURE_HIDDEN + 32 * w + 16 * mi + (lane & 15);
+        wf[layer][mi][ks] = wv[row * (CLOSURE_IN / 8) + (32 * ks + fk) / 8];
+      }
+  for (int e = tid; e < 16 * (CLOSURE_IN / 8); e += 256)
+    *reinterpret_cast<uint4*>(&W3[(e / (CLOSURE_IN / 8)) * LDW + (e % (CLOSURE_IN / 8)) * 8]) =
+        wv[2 * CLOSURE_HIDDEN * (CLOSURE_IN / 8) + e];
+  float b3[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) b3[r] = net->b3[4 * (lane >> 4) + r];
 
   const int NXE = G.nx + 1, total = NXE * (G.ny + 1);
   const int nblk = (total + CB - 1) / CB;
@@ -340,16 +365,31 @@ __global__ void __launch_bounds__(256) closure_infer_kernel(T* __restrict__ U,
     const int pt = blk * CB + lane;
     const bool live = pt < total;
     const int i = live ? pt % NXE : 0, j = live ? pt / NXE : 0;
-    C v[3][9];
+    // clamped (or wrapped) columns and rows of the stencil, per axis class:
+    // [0] cell-centred, [1] nodal
+    int colx[2][3], rowy[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      colx[0][a] = min(max(i + a - 1, 0), G.nx - 1);
+      const int xn = min(max(i + a - 1, 0), G.nx - G.px);
+      colx[1][a] = G.px ? (xn + 1 == G.nx ? 0 : xn + 1) : xn;
+      rowy[0][a] = min(max(j + a - 1, 0), G.ny - 1) * G.pitch;
+      const int yn = min(max(j + a - 1, 0), G.ny - G.py);
+      rowy[1][a] = (G.py ? (yn + 1 == G.ny ? 0 : yn + 1) : yn) * G.pitch;
+    }
+    // two passes over the stencil (the second re-reads cached values): the
+    // sum of squares, then the normalised inputs
     C ss = C(0);
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const int p = w + 4 * t;
       if (p < CLOSURE_PLANES) {
+        const T* up = U + int64_t(G.k[p]) * G.plane_stride;
+        const int cx = G.nodex[p], cy = G.nodey[p];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          stencil_value(U, G, p, i, j, q % 3 - 1, q / 3 - 1, &v[t][q]);
-          ss += v[t][q] * v[t][q];
+          const C v = to_c(up[rowy[cy][q / 3] + colx[cx][q % 3]]);
+          ss += v * v;
         }
       }
     }
@@ -357,12 +397,18 @@ __global__ void __launch_bounds__(256) closure_infer_kernel(T* __restrict__ U,
     part[w * CB + lane] = ss;
     __syncthreads();
     const C nu = sqrt(((part[lane] + part[CB + lane]) + part[2 * CB + lane]) + part[3 * CB + lane]) + C(CLOSURE_EPS);
+    const C rnu = C(1) / nu;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const int p = w + 4 * t;
       if (p < CLOSURE_PLANES) {
+        const T* up = U + int64_t(G.k[p]) * G.plane_stride;
+        const int cx = G.nodex[p], cy = G.nodey[p];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Xa[lane * LDW + 9 * p + q] = uint16_t(bf16_bits(v[t][q] / nu));
+        for (int q = 0; q < 9; ++q) {
+          const C v = to_c(up[rowy[cy][q / 3] + colx[cx][q % 3]]);
+          Xa[lane * LDW + 9 * p + q] = uint16_t(bf16_in(v * rnu));
+        }
       }
     }
     if (w == 3) {
@@ -375,65 +421,63 @@ __global__ void __launch_bounds__(256) closure_infer_kernel(T* __restrict__ U,
     }
     __syncthreads();
 
-    // 2. hidden layers: wave w computes units [32 w, 32 w + 32) of all 64 points
-    const int fk = 8 * (lane >> 4);
+    // 2. hidden layers: H^T (units x points) = W X^T; wave w: 32 units x 64 points
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
       const uint16_t* Xin = layer == 0 ? Xa : Xb;
       uint16_t* Xout = layer == 0 ? Xb : Xa;
-      const uint16_t* Wl = layer == 0 ? W1 : W2;
-      f32x4 acc[4][2];
+      f32x4 acc[2][4];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+      for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nj = 0; nj < 4; ++nj) acc[mi][nj] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int k0 = 0; k0 < CLOSURE_IN; k0 += 32) {
-        uint4 bfr[2];
+      for (int ks = 0; ks < 4; ++ks) {
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj)
-          bfr[nj] = *reinterpret_cast<const uint4*>(&Wl[(32 * w + 16 * nj + (lane & 15)) * LDW + k0 + fk]);
+        for (int nj = 0; nj < 4; ++nj) {
+          const uint4 xf = *reinterpret_cast<const uint4*>(&Xin[(16 * nj + (lane & 15)) * LDW + 32 * ks + fk]);
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-          const uint4 afr = *reinterpret_cast<const uint4*>(&Xin[(16 * mi + (lane & 15)) * LDW + k0 + fk]);
-#pragma unroll
-          for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = mfma16(afr, bfr[nj], acc[mi][nj]);
+          for (int mi = 0; mi < 2; ++mi) acc[mi][nj] = mfma16(wf[layer][mi][ks], xf, acc[mi][nj]);
         }
       }
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+      for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int m = 16 * mi + 4 * (lane >> 4) + r;
-            const int n = 32 * w + 16 * nj + (lane & 15);
-            const float z = acc[mi][nj][r] + (layer == 0 ? b1[nj] : b2[nj]);
-            Xout[m * LDW + n] = uint16_t(bf16_bits(gelu(z)));
-          }
+        for (int nj = 0; nj < 4; ++nj) {
+          // rows: units 32 w + 16 mi + 4 (lane / 16) + r; column: point 16 nj + lane % 16
+          const float4 bv = *reinterpret_cast<const float4*>((layer == 0 ? net->b1 : net->b2) + 32 * w + 16 * mi +
+                                                             4 * (lane >> 4));
+          uint32_t h[4];
+          h[0] = bf16_hw(gelu_fast(acc[mi][nj][0] + bv.x));
+          h[1] = bf16_hw(gelu_fast(acc[mi][nj][1] + bv.y));
+          h[2] = bf16_hw(gelu_fast(acc[mi][nj][2] + bv.z));
+          h[3] = bf16_hw(gelu_fast(acc[mi][nj][3] + bv.w));
+          const int m = 16 * nj + (lane & 15);
+          const int n = 32 * w + 16 * mi + 4 * (lane >> 4);
+          *reinterpret_cast<uint2*>(&Xout[m * LDW + n]) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        }
       __syncthreads();
     }
 
-    // 3. output layer: wave w takes points [16 w, 16 w + 16), 16 outputs (6 used)
+    // 3. output layer: Y^T (16 x points) = W3 X^T; wave w takes points [16 w, 16 w + 16)
     f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k0 = 0; k0 < CLOSURE_IN; k0 += 32) {
-      const uint4 afr = *reinterpret_cast<const uint4*>(&Xa[(16 * w + (lane & 15)) * LDW + k0 + fk]);
-      const uint4 bfr = *reinterpret_cast<const uint4*>(&W3[(lane & 15) * LDW + k0 + fk]);
-      y = mfma16(afr, bfr, y);
+    for (int ks = 0; ks < 4; ++ks) {
+      const uint4 af = *reinterpret_cast<const uint4*>(&W3[(lane & 15) * LDW + 32 * ks + fk]);
+      const uint4 xf = *reinterpret_cast<const uint4*>(&Xa[(16 * w + (lane & 15)) * LDW + 32 * ks + fk]);
+      y = mfma16(af, xf, y);
     }
-    const int o = lane & 15;
-    if (o < CLOSURE_OUT) {
+    const int m = 16 * w + (lane & 15);  // point of this lane
+    const int p2 = blk * CB + m;
+    if (p2 < total) {
+      const int pi = p2 % NXE, pj = p2 / NXE;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = 16 * w + 4 * (lane >> 4) + r;
-        const int p2 = blk * CB + m;
-        if (p2 >= total) continue;
-        const int pi = p2 % NXE, pj = p2 / NXE;
-        if (pi >= G.out_nx[o] || pj >= G.out_ny[o]) continue;
+        const int o = 4 * (lane >> 4) + r;  // output of this lane
+        if (o >= CLOSURE_OUT || pi >= G.out_nx[o] || pj >= G.out_ny[o]) continue;
         const int X = internal_index(pi, G.out_nodex[o], G.px, G.nx);
         const int Y = internal_index(pj, G.out_nodey[o], G.py, G.ny);
-        const C g = nu_s[m] * C(y[r] + b3) / C(G.dx);
+        const C g = nu_s[m] * C(y[r] + b3[r]) / C(G.dx);
         U[int64_t(G.q[o]) * G.plane_stride + int64_t(Y) * G.pitch + X] = from_c<T>(g);
       }
     }
@@ -503,7 +547,7 @@ hipError_t launch_closure_samples(int storage, const void* U, const void* decay,
 }
 
 size_t closure_infer_lds_bytes() {
-  return size_t(2 * CLOSURE_HIDDEN + 16 + 2 * CB) * LDW * 2 + size_t(5 * CB) * 8;
+  return size_t(2 * CB + 16) * LDW * 2 + size_t(5 * CB) * 8;
 }
 
 namespace {
@@ -527,8 +571,8 @@ hipError_t launch_infer_t(void* U, const void* decay, const ClosureGeo& G, const
 
 hipError_t launch_closure_infer(int storage, void* U, const void* decay, const ClosureGeo& G, const ClosureNet* net,
                                 hipStream_t stream) {
-  // one workgroup per compute unit (the network fills most of its LDS), each
-  // looping over blocks of points with the weights loaded once
+  // a few workgroups per compute unit, each looping over blocks of points
+  // with the weights loaded once
   static int cus = 0;
   if (!cus) {
     int dev = 0;
@@ -538,7 +582,7 @@ hipError_t launch_closure_infer(int storage, void* U, const void* decay, const C
   }
   const int total = (G.nx + 1) * (G.ny + 1);
   const int nblk = (total + CB - 1) / CB;
-  const int blocks = std::min(nblk, cus);
+  const int blocks = std::min(nblk, 3 * cus);
   switch (storage) {
     case STORE_FP64: return launch_infer_t<double>(U, decay, G, net, blocks, stream);
     case STORE_FP32: return launch_infer_t<float>(U, decay, G, net, blocks, stream);
