@@ -112,6 +112,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1211_2205_amd.build.build() "
                               "(hipcc, gfx950); there is no fallback implementation")
+        # PyTorch ships its own HIP runtime under the same soname as the system
+        # one the library links against.  Loading torch first makes the library
+        # bind to torch's copy, so the process has one runtime (shared device
+        # context and streams); the other order leaves torch on a mismatched
+        # runtime that finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, args, res in SIGNATURES:
             fn = getattr(L, name)

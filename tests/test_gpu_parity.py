@@ -106,6 +106,45 @@ def test_tile_variants_are_bitwise_identical(N, monkeypatch):
     assert ref is not None
 
 
+@pytest.mark.parametrize("case", ["checker13", "mixed9", "periodic39"])
+def test_fp32_tile_variants_are_bitwise_identical(case, monkeypatch):
+    """FP32 storage: every tile variant and several m-range widths give the
+    same bits, on extrapolated, periodic and mixed boundaries with ragged
+    grids; and match the oracle."""
+    if case == "checker13":
+        prob = wl.checkerboard(N=13, n=77, t_final=0.5, precision="fp32")
+    elif case == "mixed9":
+        prob = wl.random_medium(31, 9, 70, t_final=0.3, precision="fp32")
+        prob.n = (70, 45)
+        prob.bc = (wl.BC_PERIODIC, wl.BC_EXTRAPOLATION)
+    else:
+        prob = wl.random_medium(32, 39, 40, t_final=0.2, precision="fp32")
+        prob.n = (67, 40)
+        prob.bc = (wl.BC_PERIODIC, wl.BC_PERIODIC)
+    ref, tried = None, []
+    for width in (4, 8):
+        monkeypatch.setenv("STARMAP_CHUNK_WIDTH", str(width))
+        for v in range(6):
+            s = pa.Solver.from_problem(prob)
+            s.bind_torch()
+            try:
+                s.set_variant(v)
+            except pa.StarmapError:
+                continue
+            _say(f"  {case} variant {v} width {width}")
+            tried.append((v, width))
+            s.advance(7)
+            out = s.moments()
+            if ref is None:
+                ref = out
+            else:
+                for a, b in zip(out, ref):
+                    assert np.array_equal(a, b), f"variant {v} width {width} differs"
+    assert len(tried) >= 8
+    o = run_oracle(prob, nsteps=7)
+    assert rel_l2(ref, o.u) < FP32_TOL
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
 def test_c2_checkerboard_full_run(precision, tol):
     prob = wl.config("c2")
