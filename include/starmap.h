@@ -115,9 +115,19 @@ int starmap_closure_pn(int32_t N, int32_t axis, int32_t* cols, double* vals);
    scales the admissible time step, Sect. 4.6 and Sect. 5.3). */
 int starmap_spectral_radius(int32_t N, double* rho);
 
+/* Moments of a unit beam source delta(Omega - Omega_0) in direction
+   Omega_0 = (ox, oy, oz) (a unit vector; oz is the component out of the
+   plane): the real basis functions of the moment vector at Omega_0, from the
+   complex spherical harmonics and the change of variables of Sect. 3
+   (R_l^0 = Y_l^0, R_l^m = (-1)^m sqrt2 Re Y_l^m, I_l^m = (-1)^m sqrt2 Im Y_l^m),
+   e.g. R_0^0 = 1/sqrt(4 pi), R_1^1 = sqrt(3/(4 pi)) ox, I_1^1 = sqrt(3/(4 pi)) oy.
+   A source q(x) delta(Omega - Omega_0) has moments q(x) out[k] (the beam
+   problem of Sect. 6).  out holds (N+1)(N+2)/2 values, moment order. */
+int starmap_direction_moments(int32_t N, double ox, double oy, double oz, double* out);
+
 /* Self-check of the sweep programs the library builds for order N, tile
-   tile_x x tile_y and nchunks m ranges (with sources on three moments and
-   per-order decay): replays the staged LDS window and checks that every
+   tile_x x tile_y and nchunks m ranges (with sources on three moments, and
+   with sources on every moment, and per-order decay): replays the staged LDS window and checks that every
    coupling reads the plane the moment matrices require.  STARMAP_OK or
    STARMAP_EINVAL with the failed check in starmap_last_error(). */
 int starmap_plan_check(int32_t N, int32_t tile_x, int32_t tile_y, int32_t nchunks);

@@ -203,3 +203,28 @@ def time_step(cfl: float, dx: float, dy: float, rho: float, t_final: float):
     n = int(math.ceil(t_final / dt0 - 1e-12))
     n = max(n, 1)
     return t_final / n, n
+
+
+def direction_moments(N: int, omega):
+    """Moments of a unit-weight beam delta(Omega - Omega_0): the real basis
+    functions of the moment vector evaluated at Omega_0 = (ox, oy, oz).
+
+    From the complex spherical harmonics Y_l^m (Sect. 3, with the usual
+    Condon-Shortley phase; here scipy's sph_harm_y) the expansion coefficients
+    of the delta are psi_l^m = conj(Y_l^m(Omega_0)); the change of variables
+    to R_l^m, I_l^m (Sect. 3) gives R_l^0 = Y_l^0, R_l^m = (-1)^m sqrt2
+    Re Y_l^m, I_l^m = (-1)^m sqrt2 Im Y_l^m."""
+    from scipy.special import sph_harm_y
+    ox, oy, oz = (float(v) for v in omega)
+    polar = math.acos(max(-1.0, min(1.0, oz)))
+    azim = math.atan2(oy, ox)
+    out = []
+    for kind, l, m in moments(N):
+        y = complex(sph_harm_y(l, m, polar, azim))
+        if m == 0:
+            out.append(y.real)
+        elif kind == "R":
+            out.append((-1) ** m * math.sqrt(2.0) * y.real)
+        else:
+            out.append((-1) ** m * math.sqrt(2.0) * y.imag)
+    return np.array(out)

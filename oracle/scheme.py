@@ -145,6 +145,10 @@ class OracleSolver:
         c, q = [], []
         cache = {}
         any_q = False
+        # a beam source q(x) delta(Omega - Omega_0) has moments q(x) phi_k(Omega_0)
+        beam = None
+        if getattr(prob, "beam_direction", None) is not None:
+            beam = pn.direction_moments(self.N, prob.beam_direction)
         for k, (kind, l, m) in enumerate(self.moms):
             g = (int(self.gx[k]), int(self.gy[k]))
             if g not in cache:
@@ -160,6 +164,8 @@ class OracleSolver:
                     ck = ck - np.asarray(prob.sigma_sl(l, t, X, Y), dtype=np.float64) * np.ones(X.shape)
             c.append(np.ascontiguousarray(ck))
             f = prob.source.get(k)
+            if f is None and beam is not None and beam[k] != 0.0:
+                f = (lambda c: (lambda tt, xx, yy: c * prob.beam_profile(tt, xx, yy)))(float(beam[k]))
             if f is not None:
                 q.append(np.ascontiguousarray(np.asarray(f(t, X, Y), dtype=np.float64) * np.ones(X.shape)))
                 any_q = True

@@ -53,6 +53,8 @@ SIGNATURES = [
     ("starmap_moment_info", [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p], ctypes.c_int),
     ("starmap_closure_pn", [ctypes.c_int32, ctypes.c_int32, _i32p, _dp], ctypes.c_int),
     ("starmap_spectral_radius", [ctypes.c_int32, _dp], ctypes.c_int),
+    ("starmap_direction_moments", [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp],
+     ctypes.c_int),
     ("starmap_plan_check", [ctypes.c_int32] * 4, ctypes.c_int),
     ("starmap_create", [ctypes.POINTER(Problem), ctypes.POINTER(_vp)], ctypes.c_int),
     ("starmap_destroy", [_vp], None),

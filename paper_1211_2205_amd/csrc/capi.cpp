@@ -548,14 +548,27 @@ int starmap_plan_check(int32_t N, int32_t tile_x, int32_t tile_y, int32_t nchunk
     qk[0] = 0;  // isotropic source on the zeroth moment
     if (moment_count(N) > 3) qk[3] = 1;  // and one on an even moment of order 2
     if (moment_count(N) > 1) qk[1] = 2;  // and one on an odd moment
-    for (int p = 0; p < 2; ++p) {
-      const SweepProgram pr = build_sweep_program(N, p, tile_x, tile_y, 0.1, 0.2, rows, dm, qk, nchunks);
-      const std::string e = validate_sweep_program(N, pr, rows, qk);
-      if (!e.empty()) return fail(STARMAP_EINVAL, "sweep program check failed: " + e);
-    }
+    // and a beam: sources on every moment
+    std::vector<int32_t> all(moment_count(N));
+    for (int k = 0; k < moment_count(N); ++k) all[k] = k;
+    for (const auto* q : {&qk, &all})
+      for (int p = 0; p < 2; ++p) {
+        const SweepProgram pr = build_sweep_program(N, p, tile_x, tile_y, 0.1, 0.2, rows, dm, *q, nchunks);
+        const std::string e = validate_sweep_program(N, pr, rows, *q);
+        if (!e.empty()) return fail(STARMAP_EINVAL, "sweep program check failed: " + e);
+      }
   } catch (const std::exception& e) {
     return fail(STARMAP_EINVAL, e.what());
   }
+  return STARMAP_OK;
+}
+
+int starmap_direction_moments(int32_t N, double ox, double oy, double oz, double* out) {
+  if (N < 0 || N > 99 || !out) return fail(STARMAP_EINVAL, "bad arguments");
+  const double n2 = ox * ox + oy * oy + oz * oz;
+  if (!(std::fabs(n2 - 1.0) < 1e-9)) return fail(STARMAP_EINVAL, "direction must be a unit vector");
+  const std::vector<double> v = direction_moments(N, ox, oy, oz);
+  std::copy(v.begin(), v.end(), out);
   return STARMAP_OK;
 }
 

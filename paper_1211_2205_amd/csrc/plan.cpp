@@ -266,7 +266,8 @@ SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, d
   // descending; the window holds the input orders l + 1 and l - 1, and the
   // planes of l - 1 stay staged for output order l - 2.  Two LDS buffers of B
   // planes (selected by bit 1 of the input order), a plane of zeros for the
-  // padding couplings, and the chunk's source tiles make up the LDS.
+  // padding couplings, and the source tiles of one order's rows (staged with
+  // that order's planes) make up the LDS.
   const auto moms = moment_list(N);
   const int nmom = int(moms.size());
   SweepProgram p;
@@ -292,13 +293,17 @@ SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, d
     for (int k = 0; k < nmom; ++k)
       if (!is_out(k) && in_window(c, k)) B = std::max(B, ++cnt[moms[k].l]);
   }
+  // source tiles are staged with their order's planes: slots for the most
+  // rows with a source in one order of one chunk
+  auto has_src = [&](int k) { return !qk.empty() && qk[k] >= 0; };
   int max_src = 0;
-  for (int c = 0; c < nchunks; ++c) {
-    int n = 0;
-    for (int k = 0; k < nmom; ++k)
-      if (is_out(k) && !qk.empty() && qk[k] >= 0 && moms[k].m >= mlo[c] && moms[k].m < mhi[c]) ++n;
-    max_src = std::max(max_src, n);
-  }
+  for (int c = 0; c < nchunks; ++c)
+    for (int l = 0; l <= N; ++l) {
+      int n = 0;
+      for (int k = 0; k < nmom; ++k)
+        if (moms[k].l == l && is_out(k) && has_src(k) && moms[k].m >= mlo[c] && moms[k].m < mhi[c]) ++n;
+      max_src = std::max(max_src, n);
+    }
   p.slots = 2 * B + 1 + max_src;
   const int zero_off = 2 * B * P;
   p.zero_off = zero_off;
@@ -315,12 +320,13 @@ SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, d
         if (!is_out(k) && in_window(c, k)) pos[k] = cnt[moms[k].l]++;
     }
     auto lds_of = [&](int k) { return (((moms[k].l >> 1) & 1) * B + pos[k]) * P; };
-    // source tiles of the chunk's rows
+    // source tile slot of each row with a source: its rank among the rows of
+    // its order that have one
     std::vector<int> src_off(nmom, -1);
-    {
+    for (int l = 0; l <= N; ++l) {
       int n = 0;
       for (int k = 0; k < nmom; ++k)
-        if (is_out(k) && !qk.empty() && qk[k] >= 0 && moms[k].m >= mlo[c] && moms[k].m < mhi[c])
+        if (moms[k].l == l && is_out(k) && has_src(k) && moms[k].m >= mlo[c] && moms[k].m < mhi[c])
           src_off[k] = (2 * B + 1 + n++) * P;
     }
     // Orders are visited from the top down: every chunk of a tile starts at
@@ -355,12 +361,10 @@ SweepProgram build_sweep_program(int N, int parity, int tx, int ty, double dx, d
           p.loads.push_back(ld);
         }
       }
-      if (first) {
-        for (int k = 0; k < nmom; ++k) {
-          if (src_off[k] < 0) continue;
-          // a source tile is read at the output point itself: no halo offset
-          p.loads.push_back({nmom + qk[k], src_off[k], 0, 0});
-        }
+      for (int k : outs) {
+        if (src_off[k] < 0) continue;
+        // a source tile is read at the output point itself: no halo offset
+        p.loads.push_back({nmom + qk[k], src_off[k], 0, 0});
       }
       first = false;
       o.load1 = int(p.loads.size());
@@ -480,6 +484,39 @@ std::string validate_sweep_program(int N, const SweepProgram& p, const std::vect
     }
   }
   return std::string();
+}
+
+std::vector<double> direction_moments(int N, double ox, double oy, double oz) {
+  // Real orthonormal basis at Omega = (ox, oy, oz): with mu = oz, s = sqrt(1 - mu^2)
+  // and the azimuth phi of (ox, oy), R_l^0 = Pbar_l^0(mu), R_l^m = sqrt2 Pbar_l^m(mu)
+  // cos(m phi), I_l^m = sqrt2 Pbar_l^m(mu) sin(m phi), where Pbar_l^m is the
+  // associated Legendre function scaled to unit norm on the sphere,
+  // sqrt((2l+1)/(4pi) (l-m)!/(l+m)!) P_l^m, by the stable three-term recurrences
+  //   Pbar_m^m = sqrt((2m+1)/(2m)) s Pbar_{m-1}^{m-1},  Pbar_0^0 = 1/sqrt(4pi),
+  //   Pbar_{m+1}^m = sqrt(2m+3) mu Pbar_m^m,
+  //   Pbar_l^m = sqrt((4l^2-1)/(l^2-m^2)) (mu Pbar_{l-1}^m - sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)) Pbar_{l-2}^m).
+  const double mu = oz, sn = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+  const double phi = std::atan2(oy, ox);
+  std::vector<std::vector<double>> P(N + 1, std::vector<double>(N + 1, 0.0));
+  double pmm = 1.0 / std::sqrt(4.0 * M_PI);
+  for (int m = 0; m <= N; ++m) {
+    if (m > 0) pmm *= std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * sn;
+    P[m][m] = pmm;
+    if (m + 1 <= N) P[m + 1][m] = std::sqrt(2.0 * m + 3.0) * mu * pmm;
+    for (int l = m + 2; l <= N; ++l) {
+      const double a = std::sqrt((4.0 * l * l - 1.0) / (double(l) * l - double(m) * m));
+      const double b = std::sqrt((double(l - 1) * (l - 1) - double(m) * m) / (4.0 * (l - 1) * (l - 1) - 1.0));
+      P[l][m] = a * (mu * P[l - 1][m] - b * P[l - 2][m]);
+    }
+  }
+  std::vector<double> out;
+  for (const MomentInfo& mi : moment_list(N)) {
+    if (mi.m == 0)
+      out.push_back(P[mi.l][0]);
+    else
+      out.push_back(std::sqrt(2.0) * P[mi.l][mi.m] * (mi.imag ? std::sin(mi.m * phi) : std::cos(mi.m * phi)));
+  }
+  return out;
 }
 
 }  // namespace starmap

@@ -111,6 +111,10 @@ struct DecayMap {
 // per grid for all l >= 1.
 DecayMap decay_map(int N, bool anisotropic);
 
+// Moments of a unit beam delta(Omega - Omega_0) (the real basis functions at
+// Omega_0), in moment order.
+std::vector<double> direction_moments(int N, double ox, double oy, double oz);
+
 // Number of m ranges of the given width for order N.
 int sweep_chunk_count(int N, int width);
 

@@ -51,6 +51,14 @@ def spectral_radius(N: int) -> float:
     return r.value
 
 
+def direction_moments(N: int, omega) -> np.ndarray:
+    """Moments of a unit beam delta(Omega - omega) (real basis at omega)."""
+    out = np.zeros(num_moments(N))
+    ox, oy, oz = (float(v) for v in omega)
+    B.check(B.lib().starmap_direction_moments(N, ox, oy, oz, out.ctypes.data_as(B._dp)))
+    return out
+
+
 def _field_callback(f: Callable, keep: list):
     """Wrap f(t, x, y) -> array as a vectorised C callback."""
     def cb(ctx, t, n, xp, yp, outp):
@@ -116,6 +124,12 @@ class Solver:
                 s.set_scattering_order(l, (lambda l_: (lambda t, x, y: prob.sigma_sl(l_, t, x, y)))(l), td)
         for k, f in prob.source.items():
             s.set_source(k, f, td)
+        if getattr(prob, "beam_direction", None) is not None:
+            # a beam source q(x) delta(Omega - Omega_0): q(x) times each moment's basis value
+            w = direction_moments(prob.N, prob.beam_direction)
+            for k in range(len(w)):
+                if w[k] != 0.0 and k not in prob.source:
+                    s.set_source(k, (lambda c: (lambda t, x, y: c * prob.beam_profile(t, x, y)))(float(w[k])), td)
         for k, f in prob.initial.items():
             s.set_initial(k, f)
         return s

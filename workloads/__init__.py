@@ -51,6 +51,10 @@ class Problem:
     time_dependent: bool = False  # materials / sources depend on t
     precision: str = "fp64"
     seed: Optional[int] = None
+    # beam source q(x) delta(Omega - Omega_0): unit direction Omega_0 and q(x);
+    # each solver turns it into moment sources with its own basis values
+    beam_direction: Optional[tuple] = None
+    beam_profile: Optional[Field] = None
 
     @property
     def nmom(self) -> int:
@@ -177,6 +181,34 @@ def random_medium(seed: int, N: int, n: int, t_final: float = 0.5, cfl: float = 
         bc=(BC_EXTRAPOLATION, BC_EXTRAPOLATION), cfl=cfl, t_final=t_final,
         sigma_a=_block_field(sa, -1.0, 0.25), sigma_s0=_block_field(ss, -1.0, 0.25),
         source={0: src}, precision=precision, seed=seed)
+
+
+def beam(N: int = 9, n: int = 150, t_final: float = 0.6, s: float = 0.03, cfl: float = 0.5,
+         precision: str = "fp64") -> Problem:
+    """Beam in void and medium (Sect. 6): domain [-0.6, 0.6]^2, extrapolation
+    on all sides; void (sigma_t = 0) for x < 0.3; for x >= 0.3 no absorption
+    and Henyey-Greenstein scattering sigma_sl = 100 g^l, g = 0.85; a source
+    q(x) delta(Omega - Omega_0) with Omega_0 in the plane at angle pi/6 to the
+    x-axis and q the Gaussian of the line source (standard deviation s, unit
+    mass) at the origin; zero initial state."""
+    def medium(x):
+        return np.asarray(x) >= 0.3
+
+    def sig_a(t, x, y):
+        return np.zeros_like(np.asarray(x, dtype=np.float64))
+
+    def sig_s0(t, x, y):
+        return np.where(medium(x), 100.0, 0.0)
+
+    def sig_sl(l, t, x, y):
+        return np.where(medium(x), 100.0 * 0.85 ** l, 0.0)
+
+    ang = math.pi / 6.0
+    return Problem(
+        name=f"beam_P{N}_{n}", N=N, n=(n, n), ax=(-0.6, 0.6, -0.6, 0.6),
+        bc=(BC_EXTRAPOLATION, BC_EXTRAPOLATION), cfl=cfl, t_final=t_final,
+        sigma_a=sig_a, sigma_s0=sig_s0, sigma_sl=sig_sl, precision=precision,
+        beam_direction=(math.cos(ang), math.sin(ang), 0.0), beam_profile=gaussian_std(s))
 
 
 def batch_instance(i: int, precision: str = "fp32") -> Problem:
