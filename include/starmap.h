@@ -72,6 +72,7 @@ extern "C" {
 #define STARMAP_FIELD_SCATTERING 1 /* sigma_s0 on moment k's grid */
 #define STARMAP_FIELD_SOURCE 2     /* q_k on moment k's grid      */
 #define STARMAP_FIELD_INITIAL 3    /* u_k(t = 0)                  */
+#define STARMAP_FIELD_SCATTERING_ORDER 4 /* sigma_sl (index = order l), starmap_add_field_term only */
 
 /* Problem statement (the paper's par struct, Sect. 5.1). */
 typedef struct {
@@ -92,6 +93,10 @@ typedef struct starmap_solver starmap_solver;
    aborts the calling function with STARMAP_EINVAL. */
 typedef int (*starmap_field_fn)(void* ctx, double t, int64_t count, const double* x,
                                 const double* y, double* out);
+
+/* Time factor a(t) of a separable field term (evaluated on the host, once per
+   step). */
+typedef double (*starmap_time_fn)(void* ctx, double t);
 
 /* ---------------------------------------------------------------- host-only
    These need no GPU. */
@@ -312,6 +317,34 @@ int starmap_mlp_train_step(starmap_mlp* n, const float* x, const float* t, int32
                            double* loss);
 /* One Adam step with a given gradient (host memory); synchronises. */
 int starmap_mlp_adam_step(starmap_mlp* n, const float* grad_host, double lr);
+
+/* Time-separable fields evaluated on the device (time-dependent data,
+   Sect. 5.6).  Adds a term a(t) g(x, y) to a field: which =
+   STARMAP_FIELD_ABSORPTION, STARMAP_FIELD_SCATTERING,
+   STARMAP_FIELD_SCATTERING_ORDER (index = order l, 1 <= l <= N) or
+   STARMAP_FIELD_SOURCE (index = moment k).  A field given by terms is
+   f(t, x, y) = sum_i a_i(t) g_i(x, y).  Each g_i is sampled once (called with
+   t = 0) on every grid the field is needed on and kept on the device in the
+   compute precision; per step the host evaluates only the a_i at t + dt/2
+   and passes them to one device kernel that forms the decay planes (and the
+   source planes) as linear combinations, so a step samples and uploads no
+   plane.  Planes without a time factor are formed once.  Each step is
+   S^o_{dt/2} S^e_dt S^o_{dt/2} with the data frozen at t + dt/2.
+   Adding a term replaces a callback or array set for that field; setting the
+   field with starmap_set_* or starmap_set_field_array afterwards replaces its
+   terms.  Terms must be added before the first device call
+   (STARMAP_ESTATE), and afterwards a field given by terms cannot be changed
+   (STARMAP_ESTATE).  At most STARMAP_MAX_FIELD_TERMS terms over all fields
+   (STARMAP_EINVAL).  Ownership: the callbacks and contexts must stay valid for
+   the solver's life; the library calls them from the thread that calls it.
+   A non-finite a_i(t) fails the advancing call with STARMAP_EINVAL.  If any
+   field is a time-dependent callback (time_dependent = 1), the whole solver
+   uses the host re-sampling path instead (the terms are then summed on the
+   host).  Solvers with terms cannot join a batch or use the learned closure
+   (STARMAP_EINVAL). */
+#define STARMAP_MAX_FIELD_TERMS 32
+int starmap_add_field_term(starmap_solver* s, int32_t which, int32_t index, starmap_field_fn space,
+                           void* space_ctx, starmap_time_fn time, void* time_ctx);
 
 /* Restore the initial condition at t = 0 (step 0) on the device. */
 int starmap_reset(starmap_solver* s);

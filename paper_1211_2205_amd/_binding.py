@@ -20,6 +20,8 @@ FP64, FP32, BF16 = 0, 1, 2
 CLOSURE_PN, CLOSURE_LEARNED = 0, 1
 CLOSURE_PARAMS = 33798
 FIELD_ABSORPTION, FIELD_SCATTERING, FIELD_SOURCE, FIELD_INITIAL = 0, 1, 2, 3
+FIELD_SCATTERING_ORDER = 4
+MAX_FIELD_TERMS = 32
 
 _ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EUNSTABLE: "EUNSTABLE", ESTATE: "ESTATE"}
 
@@ -39,6 +41,8 @@ class Problem(ctypes.Structure):
 FIELD_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double))
+
+TIME_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_void_p, ctypes.c_double)
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -63,6 +67,7 @@ SIGNATURES = [
     ("starmap_set_scattering_order", [_vp, ctypes.c_int32, FIELD_FN, _vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_set_source", [_vp, ctypes.c_int32, FIELD_FN, _vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_set_initial", [_vp, ctypes.c_int32, FIELD_FN, _vp], ctypes.c_int),
+    ("starmap_add_field_term", [_vp, ctypes.c_int32, ctypes.c_int32, FIELD_FN, _vp, TIME_FN, _vp], ctypes.c_int),
     ("starmap_set_field_array", [_vp, ctypes.c_int32, ctypes.c_int32, _dp], ctypes.c_int),
     ("starmap_moment_shape", [_vp, ctypes.c_int32, _i32p, _i32p, _dp, _dp], ctypes.c_int),
     ("starmap_time", [_vp, _dp, _dp, _i64p, _i64p], ctypes.c_int),

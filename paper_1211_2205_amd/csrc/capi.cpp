@@ -75,10 +75,34 @@ int sample(const starmap_solver* s, const FieldSource& f, int gx, int gy, double
     return STARMAP_OK;
   }
   out.assign(n, 0.0);
-  if (!f.fn) return STARMAP_OK;
+  if (!f.fn && f.terms.empty()) return STARMAP_OK;
   std::vector<double> X, Y;
   grid_coords(s, gx, gy, X, Y);
+  if (!f.terms.empty()) {  // sum a_i(t) g_i(x, y)
+    std::vector<double> g(n);
+    for (const FieldTerm& term : f.terms) {
+      if (term.space(term.space_ctx, 0.0, int64_t(n), X.data(), Y.data(), g.data()) != 0)
+        return fail(STARMAP_EINVAL, "field callback reported an error");
+      const double a = term.time(term.time_ctx, t);
+      for (size_t i = 0; i < n; ++i) out[i] += a * g[i];
+    }
+    return STARMAP_OK;
+  }
   if (f.fn(f.ctx, t, int64_t(n), X.data(), Y.data(), out.data()) != 0)
+    return fail(STARMAP_EINVAL, "field callback reported an error");
+  return STARMAP_OK;
+}
+
+// The spatial part g of one term of a separable field on grid (gx, gy), or
+// (term = -1) the whole time-independent field.
+int sample_basis(const starmap_solver* s, const FieldSource& f, int term, int gx, int gy, std::vector<double>& out) {
+  if (term < 0) return sample(s, f, gx, gy, 0.0, out);
+  const size_t n = size_t(points_x(s, gx)) * points_y(s, gy);
+  out.assign(n, 0.0);
+  std::vector<double> X, Y;
+  grid_coords(s, gx, gy, X, Y);
+  const FieldTerm& t = f.terms[size_t(term)];
+  if (t.space(t.space_ctx, 0.0, int64_t(n), X.data(), Y.data(), out.data()) != 0)
     return fail(STARMAP_EINVAL, "field callback reported an error");
   return STARMAP_OK;
 }
@@ -160,6 +184,87 @@ size_t program_bytes(const SweepProgram& pr, size_t csize) {
          align256(pr.rows.size() * 64) + align256(pr.coefs.size() * csize);
 }
 
+// Time-separable fields: every decay plane, then every physical source plane,
+// as a signed sum of basis planes (one per (field, term, grid); a
+// time-independent field is one basis plane with factor 1).
+void plan_separable(starmap_solver* s) {
+  s->basis.clear();
+  s->time_terms.clear();
+  s->comb_tab.clear();
+  s->basis_ready = false;
+  s->static_done = false;
+  auto has_terms = [](const FieldSource& f) { return !f.terms.empty(); };
+  bool any = has_terms(s->absorption) || has_terms(s->scattering);
+  for (auto& kv : s->scattering_order) any = any || has_terms(kv.second);
+  for (auto& kv : s->source) any = any || has_terms(kv.second);
+  s->separable = any;
+  s->nbasis = 0;
+  if (!any) return;
+  std::map<std::pair<const FieldSource*, int>, int> tidx;
+  std::map<std::tuple<const FieldSource*, int, int>, int> bidx;
+  std::vector<int32_t> first(1, 0), entries;
+  bool dynamic = false;
+  auto add = [&](const FieldSource& f, int sign, int gx, int gy) {
+    if (!f.set()) return;
+    const int nt = int(f.terms.size());
+    for (int t = (nt ? 0 : -1); t < (nt ? nt : 0); ++t) {
+      auto key = std::make_tuple(&f, t, grid_id(gx, gy));
+      auto it = bidx.find(key);
+      if (it == bidx.end()) {
+        it = bidx.emplace(key, int(s->basis.size())).first;
+        s->basis.push_back({&f, t, gx, gy});
+      }
+      int ti = -1;
+      if (t >= 0) {
+        auto jt = tidx.find({&f, t});
+        if (jt == tidx.end()) {
+          jt = tidx.emplace(std::make_pair(&f, t), int(s->time_terms.size())).first;
+          s->time_terms.push_back(f.terms[size_t(t)]);
+        }
+        ti = jt->second;
+        dynamic = true;
+      }
+      entries.insert(entries.end(), {it->second, ti, sign});
+    }
+  };
+  std::vector<int32_t> lists[4];
+  auto close_output = [&](int dst, int which) {
+    const int o = int(first.size()) - 1;
+    first.push_back(int32_t(entries.size() / 3));
+    lists[which].insert(lists[which].end(), {o, dst});
+    if (dynamic) lists[which + 1].insert(lists[which + 1].end(), {o, dst});
+    dynamic = false;
+  };
+  // decay: sigma_a (zeroth order), sigma_a + sigma_s0 - sigma_sl (order l >= 1)
+  for (int p = 0; p < s->dmap.nplanes; ++p) {
+    const int gx = s->dmap.plane_gx[p], gy = s->dmap.plane_gy[p], l = s->dmap.plane_l[p];
+    add(s->absorption, 1, gx, gy);
+    if (l >= 1) {
+      add(s->scattering, 1, gx, gy);
+      auto it = s->scattering_order.find(l);
+      if (s->anisotropic && it != s->scattering_order.end()) add(it->second, -1, gx, gy);
+    }
+    close_output(p, 0);
+  }
+  for (auto& kv : s->source) {
+    const int k = kv.first;
+    if (s->qk[k] < 0) continue;
+    add(kv.second, 1, s->moms[k].gx, s->moms[k].gy);
+    close_output(s->qk[k], 2);
+  }
+  s->nbasis = int(s->basis.size());
+  auto& tab = s->comb_tab;
+  s->tab_first = 0;
+  tab.insert(tab.end(), first.begin(), first.end());
+  s->tab_entries = int(tab.size());
+  tab.insert(tab.end(), entries.begin(), entries.end());
+  for (int w = 0; w < 4; ++w) {
+    s->tab_list[w] = int(tab.size());
+    s->nlist[w] = int(lists[w].size() / 2);
+    tab.insert(tab.end(), lists[w].begin(), lists[w].end());
+  }
+}
+
 void layout(starmap_solver* s) {
   // decay planes and source planes
   s->dmap = decay_map(s->N, s->anisotropic);
@@ -210,6 +315,13 @@ void layout(starmap_solver* s) {
   if (s->closure) {
     s->off_net = off;
     off += align256(sizeof(ClosureNet));
+  }
+  plan_separable(s);
+  if (s->separable) {
+    s->off_basis = off;
+    off += size_t(s->nbasis) * s->plane_bytes_c();
+    s->off_comb = off;
+    off += align256(s->comb_tab.size() * 4);
   }
   s->dev_bytes = off;
 }
@@ -346,6 +458,68 @@ int default_variant(const starmap_solver* s) {
   for (int v = 0; v < sweep_variant_count(); ++v)
     if (sweep_lds_bytes(v, s->slots, s->storage) <= size_t(max_lds)) return v;
   return -1;
+}
+
+static_assert(COMBINE_MAX_TERMS >= STARMAP_MAX_FIELD_TERMS, "combine kernel holds every time factor");
+
+// Basis planes of the separable fields and their combination table.
+int upload_basis(starmap_solver* s) {
+  for (int b = 0; b < s->nbasis; ++b) {
+    const auto& bs = s->basis[size_t(b)];
+    std::vector<double> v;
+    int rc = sample_basis(s, *bs.field, bs.term, bs.gx, bs.gy, v);
+    if (rc) return rc;
+    rc = upload_plane(s, dptr(s, s->off_basis + size_t(b) * s->plane_bytes_c()), bs.gx, bs.gy, v.data(), true);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync(dptr(s, s->off_comb), s->comb_tab.data(), s->comb_tab.size() * 4, hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->basis_ready = true;
+  s->static_done = false;
+  return STARMAP_OK;
+}
+
+// Decay and source planes at time t_eval from the separable fields, on the
+// device: the first call forms every plane, later calls only those with a
+// time factor.  The time factors travel as kernel arguments.
+int combine_materials(starmap_solver* s, double t_eval) {
+  if (!s->basis_ready) {
+    int rc = upload_basis(s);
+    if (rc) return rc;
+  }
+  CombineArgs c{};
+  for (size_t i = 0; i < s->time_terms.size(); ++i) {
+    c.a[i] = s->time_terms[i].time(s->time_terms[i].time_ctx, t_eval);
+    if (!std::isfinite(c.a[i])) return fail(STARMAP_EINVAL, "time factor is not finite");
+  }
+  const int32_t* tab = reinterpret_cast<const int32_t*>(dptr(s, s->off_comb));
+  c.basis = dptr(s, s->off_basis);
+  c.first = tab + s->tab_first;
+  c.entries = tab + s->tab_entries;
+  c.plane_stride = s->plane_stride;
+  const int w = s->static_done ? 1 : 0;
+  if (s->nlist[w]) {  // decay planes, compute type
+    c.out = dptr(s, s->off_decay);
+    c.list = tab + s->tab_list[w];
+    c.nlist = s->nlist[w];
+    HIP_TRY(launch_combine(s->storage, true, c, s->stream));
+  }
+  if (s->nlist[2 + w]) {  // source planes, storage type
+    c.out = dptr(s, s->off_src);
+    c.list = tab + s->tab_list[2 + w];
+    c.nlist = s->nlist[2 + w];
+    HIP_TRY(launch_combine(s->storage, false, c, s->stream));
+  }
+  s->static_done = true;
+  s->materials_ready = true;
+  return STARMAP_OK;
+}
+
+// Materials for a time-independent or separable problem at t_eval.
+int ensure_materials(starmap_solver* s, double t_eval) {
+  if (s->separable && !s->time_dependent) return combine_materials(s, t_eval);
+  return upload_materials(s, t_eval);
 }
 
 // initial state planes (zero where no initial field is set)
@@ -485,11 +659,22 @@ int check_k(const starmap_solver* s, int k) {
   return STARMAP_OK;
 }
 
+// A field is about to change: a field with separable terms is fixed once the
+// device plan exists; any other change re-samples the basis planes.
+int field_change(starmap_solver* s, const FieldSource& f) {
+  if (s->device_ready && s->separable && !f.terms.empty())
+    return fail(STARMAP_ESTATE, "a field given by separable terms is fixed after the first device call");
+  s->basis_ready = false;
+  return STARMAP_OK;
+}
+
 int set_field(starmap_solver* s, FieldSource& f, starmap_field_fn fn, void* ctx, int td) {
-  if (s->device_ready && !td && !f.time_dependent && s->materials_ready) s->materials_ready = false;
+  int rc = field_change(s, f);
+  if (rc) return rc;
   f.fn = fn;
   f.ctx = ctx;
   f.time_dependent = td != 0;
+  f.terms.clear();
   for (int g = 0; g < 4; ++g) f.has_array[g] = false;
   if (td) s->time_dependent = true;
   s->materials_ready = false;
@@ -662,6 +847,46 @@ int starmap_set_source(starmap_solver* s, int32_t k, starmap_field_fn f, void* c
   return STARMAP_OK;
 }
 
+int starmap_add_field_term(starmap_solver* s, int32_t which, int32_t index, starmap_field_fn space,
+                           void* space_ctx, starmap_time_fn time, void* time_ctx) {
+  if (!s || !space || !time) return fail(STARMAP_EINVAL, "bad arguments");
+  if (s->device_ready) return fail(STARMAP_ESTATE, "field terms must be added before the first device call");
+  FieldSource* f = nullptr;
+  switch (which) {
+    case STARMAP_FIELD_ABSORPTION: f = &s->absorption; break;
+    case STARMAP_FIELD_SCATTERING: f = &s->scattering; break;
+    case STARMAP_FIELD_SCATTERING_ORDER:
+      if (index < 1 || index > s->N) return fail(STARMAP_EINVAL, "order must be in 1..N");
+      s->anisotropic = true;
+      f = &s->scattering_order[index];
+      break;
+    case STARMAP_FIELD_SOURCE: {
+      int rc = check_k(s, index);
+      if (rc) return rc;
+      if (s->closure && s->moms[index].l == s->N)
+        return fail(STARMAP_EINVAL, "a closure solver carries its own terms on the order-N moments; no source there");
+      f = &s->source[index];
+      break;
+    }
+    default: return fail(STARMAP_EINVAL, "unknown field selector for a separable term");
+  }
+  if (f->terms.empty()) {  // a term replaces a callback or arrays
+    f->fn = nullptr;
+    f->ctx = nullptr;
+    f->time_dependent = false;
+    for (int g = 0; g < 4; ++g) f->has_array[g] = false;
+  }
+  f->terms.push_back({space, space_ctx, time, time_ctx});
+  s->materials_ready = false;
+  layout(s);
+  if (s->time_terms.size() > size_t(STARMAP_MAX_FIELD_TERMS)) {
+    f->terms.pop_back();
+    layout(s);
+    return fail(STARMAP_EINVAL, "too many separable field terms");
+  }
+  return STARMAP_OK;
+}
+
 int starmap_set_initial(starmap_solver* s, int32_t k, starmap_field_fn f, void* ctx) {
   if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
   int rc = check_k(s, k);
@@ -697,8 +922,13 @@ int starmap_set_field_array(starmap_solver* s, int32_t which, int32_t k, const d
       break;
     default: return fail(STARMAP_EINVAL, "unknown field selector");
   }
+  if (which != STARMAP_FIELD_INITIAL) {
+    rc = field_change(s, *f);
+    if (rc) return rc;
+  }
   f->arrays[g].assign(vals, vals + n);
   f->has_array[g] = true;
+  f->terms.clear();
   if (which != STARMAP_FIELD_INITIAL) {
     s->materials_ready = false;
     if (!s->device_ready) layout(s);
@@ -750,11 +980,12 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
   if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
   if (nsteps < 0) return fail(STARMAP_EINVAL, "negative step count");
   if (nsteps == 0) return STARMAP_OK;
-  if (s->closure && s->time_dependent) return fail(STARMAP_EINVAL, "the learned closure needs time-independent data");
+  if (s->closure && (s->time_dependent || s->separable))
+    return fail(STARMAP_EINVAL, "the learned closure needs time-independent data");
   int rc = ensure_device(s);
   if (rc) return rc;
   const double dt = s->dt;
-  if (!s->time_dependent) {
+  if (!s->time_dependent && !s->separable) {
     if (!s->materials_ready) {
       rc = upload_materials(s, s->t + 0.5 * dt);
       if (rc) return rc;
@@ -765,6 +996,18 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
       rc = sweep(s, 0, dt);
       if (rc) return rc;
       rc = sweep(s, 1, i + 1 < nsteps ? dt : 0.5 * dt);
+      if (rc) return rc;
+    }
+  } else if (s->separable && !s->time_dependent) {
+    // time-separable data: decay and source planes formed on the device per step
+    for (int64_t i = 0; i < nsteps; ++i) {
+      rc = combine_materials(s, (s->steps_done + i) * dt + 0.5 * dt);
+      if (rc) return rc;
+      rc = sweep(s, 1, 0.5 * dt);
+      if (rc) return rc;
+      rc = sweep(s, 0, dt);
+      if (rc) return rc;
+      rc = sweep(s, 1, 0.5 * dt);
       if (rc) return rc;
     }
   } else {
@@ -798,7 +1041,7 @@ int starmap_sweep(starmap_solver* s, int32_t parity, double tau, int32_t nsweeps
   int rc = ensure_device(s);
   if (rc) return rc;
   if (!s->materials_ready) {
-    rc = upload_materials(s, s->t + 0.5 * s->dt);
+    rc = ensure_materials(s, s->t + 0.5 * s->dt);
     if (rc) return rc;
   }
   for (int i = 0; i < nsweeps; ++i) {
@@ -952,7 +1195,7 @@ int starmap_autotune(starmap_solver* s, int32_t sweeps) {
   int rc = ensure_device(s);
   if (rc) return rc;
   if (!s->materials_ready) {
-    rc = upload_materials(s, s->t + 0.5 * s->dt);
+    rc = ensure_materials(s, s->t + 0.5 * s->dt);
     if (rc) return rc;
   }
   int dev = 0, max_lds = 64 * 1024;
@@ -1298,7 +1541,8 @@ int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_
   std::vector<starmap_solver*> v(solvers, solvers + count);
   for (int i = 0; i < count; ++i) {
     if (!v[i]) return fail(STARMAP_EINVAL, "NULL solver in batch");
-    if (v[i]->time_dependent) return fail(STARMAP_EINVAL, "batched solvers need time-independent data");
+    if (v[i]->time_dependent || v[i]->separable)
+      return fail(STARMAP_EINVAL, "batched solvers need time-independent data");
     if (v[i]->closure) return fail(STARMAP_EINVAL, "closure solvers are not batched");
     if (v[i]->storage != v[0]->storage) return fail(STARMAP_EINVAL, "batched solvers need one storage precision");
   }

@@ -246,7 +246,7 @@ int starmap_closure_samples(starmap_solver* s, const int32_t* points, int32_t co
   rc = ensure_device(s);
   if (rc) return rc;
   if (!s->materials_ready) {
-    rc = upload_materials(s, s->t + 0.5 * s->dt);
+    rc = ensure_materials(s, s->t + 0.5 * s->dt);
     if (rc) return rc;
   }
   const size_t bytes = size_t(count) * 2 * sizeof(int32_t);

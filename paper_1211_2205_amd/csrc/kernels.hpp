@@ -71,6 +71,24 @@ hipError_t prepare_sweep(int storage, int variant, int slots);
 hipError_t launch_sweep_batch(int storage, int variant, const BatchEntry* table, const int* first, int n_active,
                               int items, int j, int slots, hipStream_t stream);
 
+// Linear combination of basis planes (compute type) into decay planes
+// (compute type) or source planes (storage type).  For each pair (o, d) of
+// list: plane d of out = sum over entries e in [first[o], first[o+1]) of
+// sign_e * factor_e * basis[b_e], where entries holds (b_e, term_e, sign_e)
+// and factor_e = a[term_e] (or 1 when term_e < 0).
+constexpr int COMBINE_MAX_TERMS = 32;
+struct CombineArgs {
+  const void* basis;
+  const int* first;
+  const int* entries;
+  const int* list;
+  void* out;
+  int64_t plane_stride;
+  int nlist;
+  double a[COMBINE_MAX_TERMS];
+};
+hipError_t launch_combine(int storage, bool to_compute_type, const CombineArgs& a, hipStream_t stream);
+
 // FP64 diagnostics of a state: mass of plane 0 (times cell area is applied on
 // the host), sum of squares and max |u| over all valid points, count of
 // non-finite values.  part must hold 4 * nblocks doubles, out 4 doubles.

@@ -30,6 +30,13 @@ int fail(int code, const std::string& msg);
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+struct FieldTerm {
+  starmap_field_fn space = nullptr;
+  void* space_ctx = nullptr;
+  starmap_time_fn time = nullptr;
+  void* time_ctx = nullptr;
+};
+
 struct FieldSource {
   starmap_field_fn fn = nullptr;
   void* ctx = nullptr;
@@ -37,8 +44,13 @@ struct FieldSource {
   // pre-sampled values on grid g = (gx-1) + 2 (gy-1), public layout
   std::array<std::vector<double>, 4> arrays;
   bool has_array[4] = {false, false, false, false};
-  bool set() const { return fn || has_array[0] || has_array[1] || has_array[2] || has_array[3]; }
+  // separable form sum a_i(t) g_i(x, y) (used instead of fn / arrays when non-empty)
+  std::vector<FieldTerm> terms;
+  bool set() const {
+    return fn || has_array[0] || has_array[1] || has_array[2] || has_array[3] || !terms.empty();
+  }
 };
+
 
 inline int grid_id(int gx, int gy) { return (gx - 1) + 2 * (gy - 1); }
 
@@ -105,6 +117,25 @@ struct starmap_solver {
   void* sample_buf = nullptr;  // device copy of training-sample points
   size_t sample_cap = 0;
 
+  // time-separable fields on the device: basis planes (compute type) and an
+  // int32 table: per output (every decay plane, then every source plane) the
+  // first of its entries; per entry (basis plane, time factor or -1, sign);
+  // four lists of (output, destination plane) pairs: all decay outputs, decay
+  // outputs with a time factor, all source outputs, source outputs with one.
+  bool separable = false;
+  size_t off_basis = 0, off_comb = 0;
+  int nbasis = 0;
+  struct Basis {
+    const starmap::detail::FieldSource* field;
+    int term;  // -1: the whole (time-independent) field
+    int gx, gy;
+  };
+  std::vector<Basis> basis;
+  std::vector<starmap::detail::FieldTerm> time_terms;
+  std::vector<int32_t> comb_tab;
+  int tab_first = 0, tab_entries = 0, tab_list[4] = {}, nlist[4] = {};
+  bool basis_ready = false, static_done = false;
+
   // plane_stride is a multiple of 128 elements, so planes of every element
   // size start 256-byte aligned and state and material planes share one
   // element stride
@@ -120,6 +151,8 @@ int points_y(const starmap_solver* s, int gy);
 char* dptr(const starmap_solver* s, size_t off);
 int ensure_device(starmap_solver* s);
 int upload_materials(starmap_solver* s, double t_eval);
+// Materials of a time-independent or separable problem at t_eval.
+int ensure_materials(starmap_solver* s, double t_eval);
 
 // Closure (closure.cpp): geometry of a solver's closure inputs, and the
 // fused closure kernel run before every odd sweep of a closure solver.

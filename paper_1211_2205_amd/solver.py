@@ -7,6 +7,7 @@ device workspace and the stream.  All computation runs in libstarmap.so.
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Callable, Optional
 
 import numpy as np
@@ -57,6 +58,25 @@ def direction_moments(N: int, omega) -> np.ndarray:
     ox, oy, oz = (float(v) for v in omega)
     B.check(B.lib().starmap_direction_moments(N, ox, oy, oz, out.ctypes.data_as(B._dp)))
     return out
+
+
+def _time_callback(a: Callable, keep: list):
+    """Wrap a(t) -> float as a C callback; an exception becomes NaN, which the
+    library reports as a non-finite time factor."""
+    def cb(ctx, t):
+        try:
+            return float(a(t))
+        except Exception:
+            import traceback
+            traceback.print_exc()
+            return math.nan
+    c = B.TIME_FN(cb)
+    keep.append(c)
+    return c
+
+
+_TERM_FIELD = {"absorption": B.FIELD_ABSORPTION, "scattering": B.FIELD_SCATTERING,
+               "scattering_order": B.FIELD_SCATTERING_ORDER, "source": B.FIELD_SOURCE}
 
 
 def _field_callback(f: Callable, keep: list):
@@ -116,14 +136,26 @@ class Solver:
         initial, time_dependent, precision (fields are f(t, x, y))."""
         s = cls(prob.N, prob.n, prob.ax, prob.bc, prob.cfl, prob.t_final,
                 precision or prob.precision, device=device, closure=closure)
-        td = int(bool(getattr(prob, "time_dependent", False)))
-        s.set_absorption(prob.sigma_a, td)
-        s.set_scattering(prob.sigma_s0, td)
+        sep = getattr(prob, "separable", None) or {}
+        # with a separable form, the fields it lists carry all time dependence
+        td = int(bool(getattr(prob, "time_dependent", False)) and not sep)
+
+        def put(key, index, setter, f):
+            terms = sep.get(key) if index is None else sep.get(key, {}).get(index)
+            if terms:
+                for a, g in terms:
+                    s.add_field_term(key, 0 if index is None else index, g, a)
+            else:
+                setter(f)
+
+        put("absorption", None, lambda f: s.set_absorption(f, td), prob.sigma_a)
+        put("scattering", None, lambda f: s.set_scattering(f, td), prob.sigma_s0)
         if getattr(prob, "sigma_sl", None) is not None:
             for l in range(1, prob.N + 1):
-                s.set_scattering_order(l, (lambda l_: (lambda t, x, y: prob.sigma_sl(l_, t, x, y)))(l), td)
+                put("scattering_order", l, lambda f, l_=l: s.set_scattering_order(l_, f, td),
+                    (lambda l_: (lambda t, x, y: prob.sigma_sl(l_, t, x, y)))(l))
         for k, f in prob.source.items():
-            s.set_source(k, f, td)
+            put("source", k, lambda f, k_=k: s.set_source(k_, f, td), f)
         if getattr(prob, "beam_direction", None) is not None:
             # a beam source q(x) delta(Omega - Omega_0): q(x) times each moment's basis value
             w = direction_moments(prob.N, prob.beam_direction)
@@ -148,6 +180,14 @@ class Solver:
     def set_source(self, k, f, time_dependent=0):
         B.check(B.lib().starmap_set_source(self._h, int(k), _field_callback(f, self._keep), None,
                                            int(time_dependent)))
+
+    def add_field_term(self, which, index, g, a):
+        """Add a(t) g(x, y) to a field ("absorption", "scattering",
+        "scattering_order" with index = l, "source" with index = k); the
+        decay and source planes of such fields are formed on the device."""
+        B.check(B.lib().starmap_add_field_term(self._h, _TERM_FIELD[which], int(index),
+                                               _field_callback(lambda t, x, y: g(x, y), self._keep), None,
+                                               _time_callback(a, self._keep), None))
 
     def set_initial(self, k, f):
         B.check(B.lib().starmap_set_initial(self._h, int(k), _field_callback(f, self._keep), None))

@@ -123,3 +123,47 @@ def test_sweep_programs_are_consistent(N, tile):
     for nchunks in sorted({1, 2, 3, 4, max(1, (N + 1) // 10), (N + 1) // 2 or 1}):
         rc = L.starmap_plan_check(N, tile[0], tile[1], nchunks)
         assert rc == 0, (N, tile, nchunks, L.starmap_last_error())
+
+
+def test_separable_terms_are_validated_on_the_host():
+    g = lambda x, y: x + 0 * y
+    a = lambda t: 1.0 + t
+    s = pa.Solver(3, (10, 10), (0, 1, 0, 1))
+    base = s.workspace_bytes()
+    for which, idx in (("absorption", 0), ("scattering", 0), ("scattering_order", 2), ("source", 1)):
+        s.add_field_term(which, idx, g, a)
+    # basis planes and the combination table take device memory
+    assert s.workspace_bytes() > base
+    L = pa._binding.lib()
+    with pytest.raises(pa.StarmapError):
+        pa._binding.check(L.starmap_add_field_term(s._h, 7, 0, pa._binding.FIELD_FN(), None,
+                                                   pa._binding.TIME_FN(), None))
+    with pytest.raises(pa.StarmapError):
+        s.add_field_term("scattering_order", 0, g, a)   # orders are 1..N
+    with pytest.raises(pa.StarmapError):
+        s.add_field_term("scattering_order", 4, g, a)
+    with pytest.raises(pa.StarmapError):
+        s.add_field_term("source", 10, g, a)           # P_3 has 10 moments
+    c = pa.Solver(5, (10, 10), (0, 1, 0, 1), closure="learned")
+    with pytest.raises(pa.StarmapError):
+        c.add_field_term("source", 20, g, a)           # order-5 moment of a closure solver
+
+
+def test_separable_term_count_is_bounded():
+    s = pa.Solver(3, (10, 10), (0, 1, 0, 1))
+    g = lambda x, y: x + 0 * y
+    for i in range(pa._binding.MAX_FIELD_TERMS):
+        s.add_field_term("absorption", 0, g, (lambda i_: (lambda t: float(i_)))(i))
+    before = s.workspace_bytes()
+    with pytest.raises(pa.StarmapError):
+        s.add_field_term("source", 0, g, lambda t: 1.0)
+    # the rejected term left the plan unchanged
+    assert s.workspace_bytes() == before
+
+
+def test_header_constants_match_binding():
+    txt = open(HEADER).read()
+    defs = dict(re.findall(r"#define (STARMAP_[A-Z0-9_]+) (\d+)", txt))
+    assert int(defs["STARMAP_FIELD_SCATTERING_ORDER"]) == pa._binding.FIELD_SCATTERING_ORDER
+    assert int(defs["STARMAP_MAX_FIELD_TERMS"]) == pa._binding.MAX_FIELD_TERMS
+    assert int(defs["STARMAP_FIELD_SOURCE"]) == pa._binding.FIELD_SOURCE

@@ -55,6 +55,11 @@ class Problem:
     # each solver turns it into moment sources with its own basis values
     beam_direction: Optional[tuple] = None
     beam_profile: Optional[Field] = None
+    # time-separable form of some fields: {"absorption": [(a, g), ...],
+    # "scattering": [...], "scattering_order": {l: [...]}, "source": {k: [...]}}
+    # with a(t) a float and g(x, y) an array; the listed fields equal
+    # sum a(t) g(x, y) (the callables above give the same values)
+    separable: Optional[dict] = None
 
     @property
     def nmom(self) -> int:
@@ -209,6 +214,73 @@ def beam(N: int = 9, n: int = 150, t_final: float = 0.6, s: float = 0.03, cfl: f
         bc=(BC_EXTRAPOLATION, BC_EXTRAPOLATION), cfl=cfl, t_final=t_final,
         sigma_a=sig_a, sigma_s0=sig_s0, sigma_sl=sig_sl, precision=precision,
         beam_direction=(math.cos(ang), math.sin(ang), 0.0), beam_profile=gaussian_std(s))
+
+
+def _sum_of_terms(terms) -> Field:
+    def f(t, x, y):
+        out = np.zeros(np.broadcast(x, y).shape)
+        for a, g in terms:
+            out = out + a(t) * g(x, y)
+        return out
+    return f
+
+
+def manufactured(n: int = 32, precision: str = "fp64", t_final: float = 0.5) -> Problem:
+    """Manufactured solution of Sect. 6.1 in time-separable form: P_3 on
+    [0,1]^2, periodic, sigma_a = t cos(2 pi y), sigma_s0 = 1,
+    sigma_sl = 0.9^l, exact R_0^0 = e^-t sin^2(2 pi x), every other moment
+    zero; the source is q_0 = R_0^0 (sigma_a - 1) and
+    q_1 = c d/dx R_0^0 with c = 1/sqrt(3) the coupling of R_1^1 to R_0^0 in
+    M_x of P_3 (the moment with index 1 is R_1^1)."""
+    c = math.sqrt(2.0) * math.sqrt(2.0 / 3.0) / 2.0
+    two_pi = 2.0 * math.pi
+    sep = {
+        "absorption": [(lambda t: t, lambda x, y: np.cos(two_pi * y) + 0 * x)],
+        "source": {
+            0: [(lambda t: t * math.exp(-t), lambda x, y: np.sin(two_pi * x) ** 2 * np.cos(two_pi * y)),
+                (lambda t: -math.exp(-t), lambda x, y: np.sin(two_pi * x) ** 2 + 0 * y)],
+            1: [(lambda t: math.exp(-t), lambda x, y: c * two_pi * np.sin(2 * two_pi * x) + 0 * y)],
+        },
+    }
+    exact = lambda t, x, y: math.exp(-t) * np.sin(two_pi * x) ** 2 + 0 * y
+    return Problem(
+        name=f"manufactured_P3_{n}", N=3, n=(n, n), ax=(0.0, 1.0, 0.0, 1.0), bc=(BC_PERIODIC, BC_PERIODIC),
+        cfl=0.5, t_final=t_final, sigma_a=_sum_of_terms(sep["absorption"]), sigma_s0=_const(1.0),
+        sigma_sl=lambda l, t, x, y: np.full(np.broadcast(x, y).shape, 0.9 ** l),
+        source={k: _sum_of_terms(v) for k, v in sep["source"].items()}, initial={0: exact},
+        time_dependent=True, precision=precision, separable=sep)
+
+
+def pulsed_medium(seed: int, N: int, n: int, t_final: float = 0.4, precision: str = "fp64") -> Problem:
+    """Heterogeneous time-dependent medium in separable form (no counterpart
+    in the paper; a stress case for time-dependent data): on [-1,1]^2 with
+    extrapolation boundaries, absorption = 8x8 random blocks in [0,2] plus
+    three oscillating terms (1 + sin(w t + p)) times random blocks in [0,1],
+    scattering = random blocks in [0,5] times (1 + t/2), anisotropic
+    scattering sigma_sl = g^l times the scattering blocks times (1 - t/4)
+    with g = 0.6, and a zeroth-moment source of two Gaussian pulses e^-(t-tc)^2/w^2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    blocks = lambda hi: _block_field(rng.uniform(0.0, hi, size=(8, 8)), -1.0, 0.25)
+    base = blocks(2.0)
+    absorption = [(lambda t: 1.0, lambda x, y, f=base: f(0.0, x, y))]
+    for _ in range(3):
+        w, p, f = rng.uniform(5.0, 20.0), rng.uniform(0.0, 2 * math.pi), blocks(1.0)
+        absorption.append((lambda t, w=w, p=p: 1.0 + math.sin(w * t + p), lambda x, y, f=f: f(0.0, x, y)))
+    fs = blocks(5.0)
+    scattering = [(lambda t: 1.0 + 0.5 * t, lambda x, y: fs(0.0, x, y))]
+    order = {l: [(lambda t: 1.0 - 0.25 * t, lambda x, y, l=l: 0.6 ** l * fs(0.0, x, y))] for l in range(1, N + 1)}
+    src = []
+    for _ in range(2):
+        cx, cy, tc = rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), rng.uniform(0.0, t_final)
+        g = gaussian_std(0.1, cx, cy)
+        src.append((lambda t, tc=tc: math.exp(-((t - tc) / 0.1) ** 2), lambda x, y, g=g: g(0.0, x, y)))
+    sep = {"absorption": absorption, "scattering": scattering, "scattering_order": order, "source": {0: src}}
+    return Problem(
+        name=f"pulsed_medium_s{seed}_P{N}_{n}", N=N, n=(n, n), ax=(-1.0, 1.0, -1.0, 1.0),
+        bc=(BC_EXTRAPOLATION, BC_EXTRAPOLATION), cfl=0.5, t_final=t_final,
+        sigma_a=_sum_of_terms(absorption), sigma_s0=_sum_of_terms(scattering),
+        sigma_sl=lambda l, t, x, y: _sum_of_terms(order[l])(t, x, y), source={0: _sum_of_terms(src)},
+        time_dependent=True, precision=precision, seed=seed, separable=sep)
 
 
 def batch_instance(i: int, precision: str = "fp32") -> Problem:
