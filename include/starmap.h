@@ -227,9 +227,15 @@ int starmap_diagnostics(const starmap_solver* s, double* mass_r00, double* l2, d
                         int32_t* nonfinite);
 
 /* Tile variant of the sweep kernel: -1 chooses by the autotuner (default).
-   starmap_autotune times every variant that fits on a few sweeps of this
-   solver, keeps the fastest and writes it to the cache file named by the
-   environment variable STARMAP_TUNE_CACHE (if set). */
+   Variants differ in the spatial tile (tile_x x tile_y points) and in how
+   many planes of one order are held in registers while the next order loads
+   (fewer registers let more workgroups share a compute unit); all give the
+   same bits.  starmap_autotune times every variant that fits, at every
+   m-range width (4, 6, 8), on a few sweeps of this solver, keeps the fastest
+   pair and writes it to the cache file named by the environment variable
+   STARMAP_TUNE_CACHE (if set).  Variants are 0 .. starmap_variant_count()-1;
+   another value fails with STARMAP_EINVAL. */
+int starmap_variant_count(void);
 int starmap_set_variant(starmap_solver* s, int32_t variant);
 int starmap_get_variant(const starmap_solver* s, int32_t* variant, int32_t* tile_x, int32_t* tile_y);
 int starmap_autotune(starmap_solver* s, int32_t sweeps_per_variant);

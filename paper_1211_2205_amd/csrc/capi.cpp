@@ -1152,6 +1152,8 @@ int starmap_diagnostics(const starmap_solver* cs, double* mass, double* l2, doub
   return STARMAP_OK;
 }
 
+int starmap_variant_count(void) { return sweep_variant_count(); }
+
 int starmap_set_variant(starmap_solver* s, int32_t v) {
   if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
   if (v < -1 || v >= sweep_variant_count()) return fail(STARMAP_EINVAL, "unknown variant");

@@ -361,8 +361,13 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
 
 // ------------------------------------------------------------ variants
 namespace {
-constexpr TileShape kVariants[] = {{64, 4, 10}, {128, 2, 10}, {32, 8, 10}, {32, 16, 10},
-                                   {128, 4, 10}, {64, 8, 10}};
+// (tx, ty, cap): cap 10 holds the widest m range's planes of one order in
+// registers; cap 8 and 6 hold fewer (the rest is staged synchronously) but
+// leave registers for a fourth (fifth) workgroup per CU, which pays at the
+// narrower m ranges
+constexpr TileShape kVariants[] = {{64, 4, 10},  {128, 2, 10}, {32, 8, 10}, {32, 16, 10}, {128, 4, 10},
+                                   {64, 8, 10},  {64, 8, 8},   {64, 8, 6},  {32, 8, 8},   {32, 8, 6},
+                                   {64, 4, 8},   {32, 16, 8},  {128, 4, 8}, {64, 4, 6}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Opt the kernels of one instantiation in to all of the device's LDS (once).
@@ -436,6 +441,14 @@ hipError_t launch_batch_t(const BatchEntry* table, const int* first, int n_activ
     case 3: return CALL(32, 16, 10);      \
     case 4: return CALL(128, 4, 10);      \
     case 5: return CALL(64, 8, 10);       \
+    case 6: return CALL(64, 8, 8);        \
+    case 7: return CALL(64, 8, 6);        \
+    case 8: return CALL(32, 8, 8);        \
+    case 9: return CALL(32, 8, 6);        \
+    case 10: return CALL(64, 4, 8);       \
+    case 11: return CALL(32, 16, 8);      \
+    case 12: return CALL(128, 4, 8);      \
+    case 13: return CALL(64, 4, 6);       \
   }                                       \
   return hipErrorInvalidValue;
 

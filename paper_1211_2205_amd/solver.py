@@ -18,6 +18,11 @@ _PREC = {"fp64": B.FP64, "fp32": B.FP32, "bf16": B.BF16}
 _BC = {"periodic": B.BC_PERIODIC, "extrapolation": B.BC_EXTRAPOLATION}
 
 
+def variant_count() -> int:
+    """Number of compiled tile variants of the sweep kernel."""
+    return int(B.lib().starmap_variant_count())
+
+
 def num_moments(N: int) -> int:
     return B.check(B.lib().starmap_num_moments(N))
 

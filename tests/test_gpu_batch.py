@@ -91,7 +91,7 @@ def test_batch_eager_graph_and_rerun_agree():
     b.close()
 
 
-@pytest.mark.parametrize("variant,width", [(1, 4), (3, 6), (5, 4)])
+@pytest.mark.parametrize("variant,width", [(1, 4), (3, 6), (5, 4), (6, 6), (13, 4)])
 def test_batch_tile_variants(variant, width, monkeypatch):
     probs = _mixed()
     solvers = [pa.Solver.from_problem(p) for p in probs]
@@ -109,7 +109,7 @@ def test_batch_fp32_and_autotune(monkeypatch):
     b = pa.Batch(solvers)
     b.autotune(2)
     v, w = b.variant()
-    assert 0 <= v < 6 and w in (4, 6, 8)
+    assert 0 <= v < pa.variant_count() and w in (4, 6, 8)
     b.run()
     for p, s in zip(probs, solvers):
         g = s.moments()

@@ -89,7 +89,7 @@ def test_tile_variants_are_bitwise_identical(N, monkeypatch):
     ref = None
     for width in (2, 5, 8, 12):
         monkeypatch.setenv("STARMAP_CHUNK_WIDTH", str(width))
-        for v in range(6):
+        for v in range(pa.variant_count()):
             s = pa.Solver.from_problem(prob)
             s.bind_torch()
             try:
@@ -124,7 +124,7 @@ def test_fp32_tile_variants_are_bitwise_identical(case, monkeypatch):
     ref, tried = None, []
     for width in (4, 8):
         monkeypatch.setenv("STARMAP_CHUNK_WIDTH", str(width))
-        for v in range(6):
+        for v in range(pa.variant_count()):
             s = pa.Solver.from_problem(prob)
             s.bind_torch()
             try:

@@ -167,3 +167,13 @@ def test_header_constants_match_binding():
     assert int(defs["STARMAP_FIELD_SCATTERING_ORDER"]) == pa._binding.FIELD_SCATTERING_ORDER
     assert int(defs["STARMAP_MAX_FIELD_TERMS"]) == pa._binding.MAX_FIELD_TERMS
     assert int(defs["STARMAP_FIELD_SOURCE"]) == pa._binding.FIELD_SOURCE
+
+
+def test_tile_variants_are_enumerable():
+    n = pa.variant_count()
+    assert n >= 6
+    s = pa.Solver(3, (40, 30), (0, 1, 0, 1))
+    for v in range(n):
+        s.set_variant(v)  # P_3 fits every tile within the 64 KiB assumed without a device
+    with pytest.raises(pa.StarmapError, match="unknown variant"):
+        s.set_variant(n)
