@@ -38,6 +38,21 @@ struct SweepScalars {
   C tau;
 };
 
+// Output values are written once per sweep and not read again before the
+// next sweep: stream them past the caches.
+__device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(bf16* p, bf16 v) {
+  __builtin_nontemporal_store(v.bits, reinterpret_cast<uint16_t*>(p));
+}
+
+// Output rows are read once per sweep, just before they are overwritten.
+__device__ __forceinline__ float load_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double load_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ bf16 load_stream(const bf16* p) {
+  return bf16{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
+}
+
 // Body of one workgroup's work in a sweep: spatial tile and m range number lb
 // (lb = tile * nchunks + range) of one instance.
 template <typename T, int TX, int TY, int CAP>
@@ -179,7 +194,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const T* up = U + int64_t(rec[0]) * a.plane_stride;
         const bool s1 = rec[1] != 0;
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(up[goff[p]]) : C(0);
+        for (int p = 0; p < PPT; ++p) uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(load_stream(&up[goff[p]])) : C(0);
       }
     }
   };
@@ -261,7 +276,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
               const C c = gslot ? c1[p] : c0[p];
               const C E = gslot ? e1[p] : e0[p];
               const C u = ua[i][p];
-              up[goff[p]] = from_c<T>(u + a.tau * (W - c * u) * E);
+              store_stream(&up[goff[p]], from_c<T>(u + a.tau * (W - c * u) * E));
             }
           }
         }
