@@ -10,6 +10,17 @@ it (Sect. 5.7), recompute the odd residual, S^o_{dt/2}.  The optional `fused`
 composition instead applies S^o_{dt/2}, [S^e_{dt}, S^o_{dt}]^(n-1), S^e_{dt},
 S^o_{dt/2}; with frozen data both compositions are equal in exact arithmetic.
 
+Two moment models of the paper's outlook (Sect. 7) use the same scheme:
+  * filtered P_N (FP_N): per-order filter damping d_l added to the decay
+    coefficient of every moment of order l (problem field `filter_damping`);
+  * diffusion-corrected P_N (D_N): a diffusion step on the moments of the
+    highest order, placed between the two even half-steps of every step:
+    S^o_{dt/2} S^e_{dt/2} D_{dt} S^e_{dt/2} S^o_{dt/2}, with
+    D_tau u = u + tau kappa (D_xx u + D_yy u) on each moment's own grid
+    (three-point second differences; periodic axes wrap, extrapolation axes
+    repeat the boundary value as ghost), explicit in time (problem field
+    `diffusion` = kappa(x, y)).
+
 Arrays follow the paper's index ranges per grid (cell index 1..n at (i-1/2)h,
 node index p..n at i h; position 0 holds the first index), shape (rows, cols)
 with x fastest.
@@ -162,6 +173,9 @@ class OracleSolver:
                 ck = sa + s0
                 if prob.sigma_sl is not None:
                     ck = ck - np.asarray(prob.sigma_sl(l, t, X, Y), dtype=np.float64) * np.ones(X.shape)
+            damping = getattr(prob, "filter_damping", None)
+            if damping is not None:  # FP_N: the filter's damping of order l
+                ck = ck + float(damping[l])
             c.append(np.ascontiguousarray(ck))
             f = prob.source.get(k)
             if f is None and beam is not None and beam[k] != 0.0:
@@ -217,13 +231,42 @@ class OracleSolver:
         if self.prob.time_dependent or self._c is None:
             self.evaluate_materials(t + 0.5 * self.dt)
 
+    def diffuse(self, tau):
+        """D_N diffusion step on every moment of order N: u <- u + tau kappa
+        (second difference along x / dx^2 + along y / dy^2), the differences
+        taken on the moment's own grid; a periodic axis wraps, an
+        extrapolation axis repeats the boundary point as its ghost."""
+        g = self.grid
+        for k, (kind, l, m) in enumerate(self.moms):
+            if l != self.N:
+                continue
+            X, Y = g.coords(self.gx[k], self.gy[k])
+            kap = np.asarray(self.prob.diffusion(0.0, X, Y), dtype=np.float64) * np.ones(X.shape)
+            u = self.u[k]
+            if g.px:
+                east, west = np.roll(u, -1, axis=1), np.roll(u, 1, axis=1)
+            else:
+                east = np.concatenate([u[:, 1:], u[:, -1:]], axis=1)
+                west = np.concatenate([u[:, :1], u[:, :-1]], axis=1)
+            if g.py:
+                north, south = np.roll(u, -1, axis=0), np.roll(u, 1, axis=0)
+            else:
+                north = np.concatenate([u[1:, :], u[-1:, :]], axis=0)
+                south = np.concatenate([u[:1, :], u[:-1, :]], axis=0)
+            lap = (east - 2.0 * u + west) / (g.dx * g.dx) + (north - 2.0 * u + south) / (g.dy * g.dy)
+            self.u[k] = np.ascontiguousarray(u + tau * kap * lap)
+
     def step(self):
-        """One full step t -> t + dt: S^o_{dt/2} S^e_{dt/2} S^e_{dt/2} S^o_{dt/2}."""
+        """One full step t -> t + dt: S^o_{dt/2} S^e_{dt/2} S^e_{dt/2} S^o_{dt/2}
+        (with a D_N diffusion step D_dt between the two even half-steps)."""
         h = 0.5 * self.dt
         self._materials_for_step(self.t)
         self.half_step(1, h)
         We = self.flux(0)
         self.half_step(0, h, We)
+        if getattr(self.prob, "diffusion", None) is not None:
+            self.diffuse(self.dt)
+            We = None  # the diffusion changed moments the even residual reads
         self.half_step(0, h, We)
         self.half_step(1, h)
         self.step_count += 1
@@ -242,6 +285,7 @@ class OracleSolver:
                     callback(self)
             return
         assert not self.prob.time_dependent
+        assert getattr(self.prob, "diffusion", None) is None, "the D_N step splits the even half-steps"
         self._materials_for_step(self.t)
         dt = self.dt
         self.half_step(1, 0.5 * dt)

@@ -329,3 +329,100 @@ def test_fused_composition_equals_literal():
     num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(a.u, b.u))
     den = sum(float(np.sum(x ** 2)) for x in a.u)
     assert math.sqrt(num / den) < 1e-13
+
+
+# ------------------------------------------------ FP_N and D_N (Sect. 7 outlook)
+@pytest.mark.parametrize("k", [0, 3, 9, 14])
+def test_filter_damping_decays_a_uniform_moment_exactly(k):
+    """A spatially uniform moment has zero differences, so each half-step
+    multiplies it by exp(-c tau) exactly: with filter damping d_l the decay
+    rate of an order-l moment is sigma_a + sigma_s0 + d_l (l >= 1), or
+    sigma_a + d_0 for the zeroth moment."""
+    N = 4
+    l = pn.moments(N)[k][1]
+    d = wl.filter_damping(N, 7.0, power=2)
+    d[0] = 0.3
+    prob = _problem(N, (12, 10), (0, 1, 0, 2), PER, 0.25, 1.5, t_final=0.4, initial={k: _const(2.0)})
+    prob.filter_damping = d
+    o = OracleSolver(prob)
+    o.run()
+    rate = 0.25 + d[0] if l == 0 else 0.25 + 1.5 + d[l]
+    exact = 2.0 * math.exp(-rate * 0.4)
+    np.testing.assert_allclose(o.u[k], exact, rtol=1e-13)
+    for j in range(o.nmom):
+        if j != k:
+            assert np.max(np.abs(o.u[j])) < 1e-14
+    # and damping zero reproduces plain P_N exactly
+    prob.filter_damping = [0.0] * (N + 1)
+    a = OracleSolver(prob)
+    a.run()
+    prob.filter_damping = None
+    b = OracleSolver(prob)
+    b.run()
+    for x, y in zip(a.u, b.u):
+        assert np.array_equal(x, y)
+
+
+def _order_n_moments(o):
+    return [k for k, (_, l, _) in enumerate(o.moms) if l == o.N]
+
+
+@pytest.mark.parametrize("n", [(16, 12), (15, 20)])
+def test_diffusion_step_has_the_discrete_fourier_symbol(n):
+    """On a periodic grid a Fourier mode is an eigenvector of the three-point
+    second difference: D_tau multiplies exp(i(a x + b y)) by
+    1 - tau kappa (4/dx^2 sin^2(a dx/2) + 4/dy^2 sin^2(b dy/2)), on cell and
+    nodal grids alike."""
+    kappa = 0.01
+    prob = _problem(3, n, (0, 1, 0, 1.5), PER, 0.0, 0.0, t_final=0.1)
+    prob.diffusion = _const(kappa)
+    o = OracleSolver(prob)
+    ks = _order_n_moments(o)
+    a, b = 2 * math.pi * 3, 2 * math.pi * 2 / 1.5
+    for k in ks:
+        X, Y = o.grid.coords(o.gx[k], o.gy[k])
+        o.u[k] = np.ascontiguousarray(np.cos(a * X + b * Y))
+    tau = 0.7 * o.dt
+    o.diffuse(tau)
+    g = o.grid
+    lam = 1 - tau * kappa * (4 / g.dx ** 2 * math.sin(a * g.dx / 2) ** 2 + 4 / g.dy ** 2 * math.sin(b * g.dy / 2) ** 2)
+    for k in ks:
+        X, Y = o.grid.coords(o.gx[k], o.gy[k])
+        np.testing.assert_allclose(o.u[k], lam * np.cos(a * X + b * Y), rtol=0, atol=1e-13)
+
+
+def test_diffusion_step_conserves_cell_sums_and_constants():
+    """With repeated-boundary ghosts the second difference of a cell-centred
+    plane sums to zero (no flux through the boundary), and constants are left
+    unchanged on every grid."""
+    prob = _problem(4, (13, 9), (0, 1, 0, 1), EXT, 0.0, 0.0, t_final=0.1)
+    prob.diffusion = lambda t, x, y: 0.002 * (1.0 + 0 * x + 0 * y)
+    o = OracleSolver(prob)
+    rng = np.random.Generator(np.random.PCG64(3))
+    ks = _order_n_moments(o)
+    before = {}
+    for k in ks:
+        if o.gx[k] == 1 and o.gy[k] == 1:
+            o.u[k] = np.ascontiguousarray(rng.normal(size=o.u[k].shape))
+        else:
+            o.u[k] = np.full(o.u[k].shape, 3.5)
+        before[k] = o.u[k].copy()
+    o.diffuse(o.dt)
+    assert any(o.gx[k] == 1 and o.gy[k] == 1 for k in ks)
+    for k in ks:
+        if o.gx[k] == 1 and o.gy[k] == 1:
+            assert abs(o.u[k].sum() - before[k].sum()) < 1e-12
+            assert not np.allclose(o.u[k], before[k])
+        else:
+            np.testing.assert_array_equal(o.u[k], before[k])
+
+
+def test_zero_diffusion_is_plain_pn():
+    prob = wl.line_source(N=5, n=30, s=0.1, t_final=0.2)
+    a = OracleSolver(prob)
+    a.run()
+    prob.diffusion = _const(0.0)
+    b = OracleSolver(prob)
+    b.run()
+    for x, y in zip(a.u, b.u):
+        assert np.array_equal(x, y)

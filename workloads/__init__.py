@@ -60,6 +60,11 @@ class Problem:
     # with a(t) a float and g(x, y) an array; the listed fields equal
     # sum a(t) g(x, y) (the callables above give the same values)
     separable: Optional[dict] = None
+    # filtered P_N: damping d_l (l = 0..N) added to the decay of every order-l moment
+    filter_damping: Optional[Sequence[float]] = None
+    # diffusion-corrected P_N: coefficient kappa(x, y) of the diffusion step on
+    # the order-N moments (time-independent; called with t = 0)
+    diffusion: Optional[Field] = None
 
     @property
     def nmom(self) -> int:
@@ -281,6 +286,12 @@ def pulsed_medium(seed: int, N: int, n: int, t_final: float = 0.4, precision: st
         sigma_a=_sum_of_terms(absorption), sigma_s0=_sum_of_terms(scattering),
         sigma_sl=lambda l, t, x, y: _sum_of_terms(order[l])(t, x, y), source={0: _sum_of_terms(src)},
         time_dependent=True, precision=precision, seed=seed, separable=sep)
+
+
+def filter_damping(N: int, strength: float, power: int = 4) -> list:
+    """Per-order damping of an exponential-type filter of the given strength:
+    d_l = strength (l / (N + 1))^power, l = 0..N."""
+    return [strength * (l / (N + 1.0)) ** power for l in range(N + 1)]
 
 
 def batch_instance(i: int, precision: str = "fp32") -> Problem:
