@@ -99,6 +99,52 @@ def batch_leg(count, precision):
     return out
 
 
+def models_leg(config, precision, steps):
+    """The moment models of the paper's outlook on the same workload: plain
+    P_N, filtered P_N (damping 10 (l/(N+1))^4 per order: the decay planes
+    change, the kernels do not), diffusion-corrected P_N (kappa = 0.1 dx:
+    each step adds an even sweep split and the diffusion kernels on the N + 1
+    order-N moments), and time-dependent absorption in separable form (per
+    step the decay planes are combined on the device and the odd half-steps
+    no longer merge).  Per model: updates/s over `steps` timed steps after
+    two untimed ones, each solver autotuned."""
+    import torch
+
+    import paper_1211_2205_amd as pa
+    import workloads as wl
+    out = {}
+    for model in ("pn", "fpn", "dn", "separable"):
+        prob = wl.config(config, precision=precision)
+        if model == "fpn":
+            prob.filter_damping = wl.filter_damping(prob.N, 10.0)
+        elif model == "dn":
+            h = (prob.ax[1] - prob.ax[0]) / prob.n[0]
+            prob.diffusion = (lambda k: (lambda t, x, y: k + 0 * x))(0.1 * h)
+        elif model == "separable":
+            # time-dependent absorption 0.1 (1 + 0.5 sin(2 pi t)) (1 + x^2) in separable form
+            term = (lambda t: 0.1 * (1.0 + 0.5 * math.sin(2.0 * math.pi * t)), lambda x, y: 1.0 + x * x + 0 * y)
+            prob.separable = {"absorption": [term]}
+            prob.sigma_a = lambda t, x, y: term[0](t) * term[1](x, y)
+            prob.time_dependent = True
+        s = pa.Solver.from_problem(prob)
+        s.bind_torch()
+        s.autotune(1)
+        s.advance(2)
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(steps)
+        s.synchronize()
+        wall = time.perf_counter() - t0
+        nx, ny = prob.n
+        v, tx, ty = s.variant()
+        out[model] = {"value": nx * ny * s.nmom * steps / wall, "unit": "cell-moment updates/s",
+                      "ms_per_step": wall / steps * 1e3, "steps": steps, "tile": [tx, ty]}
+        s.close()
+    out["workload"] = f"{wl.config(config).name}_{precision}"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +156,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=200, help="rows of the oracle's CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0: skip it)")
+    ap.add_argument("--models-steps", type=int, default=20,
+                    help="timed steps of the FP_N / D_N model leg (0: skip it)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a device copy of this size (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -193,6 +241,8 @@ def main():
         "state_check": {"mass": diag["mass"], "l2": diag["l2"], "nonfinite": diag["nonfinite"]},
     }
     s.close()
+    if args.models_steps > 0:
+        out["models"] = models_leg(args.config, prec, args.models_steps)
     if args.batch > 0:
         out["batch"] = batch_leg(args.batch, "fp32")
     if not args.no_cpu_baseline:

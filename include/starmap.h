@@ -352,6 +352,34 @@ int starmap_mlp_adam_step(starmap_mlp* n, const float* grad_host, double lr);
 int starmap_add_field_term(starmap_solver* s, int32_t which, int32_t index, starmap_field_fn space,
                            void* space_ctx, starmap_time_fn time, void* time_ctx);
 
+/* Filtered P_N (FP_N; one of the moment models the paper names as fitting
+   the same scheme, Sect. 7): damping[l] >= 0 for l = 0..N (N + 1 values,
+   copied) is added to the decay coefficient of every moment of order l, so
+   that order l decays with sigma_a + damping[0] (l = 0) or
+   sigma_a + sigma_s0 - sigma_sl + damping[l] (l >= 1).  The values come from
+   the filter of the user's choice (a filter f with strength sigma_f gives
+   damping[l] = -sigma_f log f(l / (N + 1))).  The damping enters the decay
+   planes, so the sweep kernels are unchanged.  It needs per-order decay planes:
+   the first call must come before the first device call (STARMAP_ESTATE);
+   later calls change the values.  Negative or non-finite values:
+   STARMAP_EINVAL.  damping = NULL removes the damping. */
+int starmap_set_filter_damping(starmap_solver* s, const double* damping);
+
+/* Diffusion-corrected P_N (D_N; Sect. 7: a diffusion step on the moments of
+   the highest order fits the splitting): every step becomes
+   S^o_{dt/2} S^e_{dt/2} D_dt S^e_{dt/2} S^o_{dt/2} with
+   D_tau u = u + tau kappa (D_xx u + D_yy u) on each order-N moment's own grid
+   (three-point second differences with dx^2, dy^2; periodic axes wrap,
+   extrapolation axes repeat the boundary point as ghost), explicit in time.
+   kappa(x, y) >= 0 is sampled once (t = 0) on the order-N grids; the first
+   device call fails with STARMAP_EINVAL if kappa is negative or not finite,
+   or if max kappa * dt * (2/dx^2 + 2/dy^2) > 1 (the explicit step would be
+   unstable).  Must be set before the first device call (STARMAP_ESTATE);
+   f = NULL removes it.  Not with the learned closure or in a batch
+   (STARMAP_EINVAL).  The callback and ctx must stay valid until the first
+   device call. */
+int starmap_set_diffusion(starmap_solver* s, starmap_field_fn kappa, void* ctx);
+
 /* Restore the initial condition at t = 0 (step 0) on the device. */
 int starmap_reset(starmap_solver* s);
 

@@ -67,6 +67,8 @@ SIGNATURES = [
     ("starmap_set_scattering_order", [_vp, ctypes.c_int32, FIELD_FN, _vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_set_source", [_vp, ctypes.c_int32, FIELD_FN, _vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_set_initial", [_vp, ctypes.c_int32, FIELD_FN, _vp], ctypes.c_int),
+    ("starmap_set_filter_damping", [_vp, _dp], ctypes.c_int),
+    ("starmap_set_diffusion", [_vp, FIELD_FN, _vp], ctypes.c_int),
     ("starmap_add_field_term", [_vp, ctypes.c_int32, ctypes.c_int32, FIELD_FN, _vp, TIME_FN, _vp], ctypes.c_int),
     ("starmap_set_field_array", [_vp, ctypes.c_int32, ctypes.c_int32, _dp], ctypes.c_int),
     ("starmap_moment_shape", [_vp, ctypes.c_int32, _i32p, _i32p, _dp, _dp], ctypes.c_int),

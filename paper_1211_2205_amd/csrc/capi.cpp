@@ -187,6 +187,12 @@ size_t program_bytes(const SweepProgram& pr, size_t csize) {
 // Time-separable fields: every decay plane, then every physical source plane,
 // as a signed sum of basis planes (one per (field, term, grid); a
 // time-independent field is one basis plane with factor 1).
+// Filter damping of the decay plane of order l (l = -1: the zeroth moment).
+double order_damping(const starmap_solver* s, int l) {
+  if (s->damping.empty()) return 0.0;
+  return s->damping[size_t(l < 0 ? 0 : l)];
+}
+
 void plan_separable(starmap_solver* s) {
   s->basis.clear();
   s->time_terms.clear();
@@ -228,9 +234,11 @@ void plan_separable(starmap_solver* s) {
     }
   };
   std::vector<int32_t> lists[4];
-  auto close_output = [&](int dst, int which) {
+  s->comb_cst.clear();
+  auto close_output = [&](int dst, int which, double cst) {
     const int o = int(first.size()) - 1;
     first.push_back(int32_t(entries.size() / 3));
+    s->comb_cst.push_back(cst);
     lists[which].insert(lists[which].end(), {o, dst});
     if (dynamic) lists[which + 1].insert(lists[which + 1].end(), {o, dst});
     dynamic = false;
@@ -244,13 +252,13 @@ void plan_separable(starmap_solver* s) {
       auto it = s->scattering_order.find(l);
       if (s->anisotropic && it != s->scattering_order.end()) add(it->second, -1, gx, gy);
     }
-    close_output(p, 0);
+    close_output(p, 0, order_damping(s, l));
   }
   for (auto& kv : s->source) {
     const int k = kv.first;
     if (s->qk[k] < 0) continue;
     add(kv.second, 1, s->moms[k].gx, s->moms[k].gy);
-    close_output(s->qk[k], 2);
+    close_output(s->qk[k], 2, 0.0);
   }
   s->nbasis = int(s->basis.size());
   auto& tab = s->comb_tab;
@@ -321,7 +329,16 @@ void layout(starmap_solver* s) {
     s->off_basis = off;
     off += size_t(s->nbasis) * s->plane_bytes_c();
     s->off_comb = off;
-    off += align256(s->comb_tab.size() * 4);
+    off += align256(s->comb_tab.size() * 4) + align256(s->comb_cst.size() * 8);
+  }
+  if (s->has_diffusion) {
+    const size_t nd = size_t(s->N + 1);
+    s->off_dtmp = off;
+    off += nd * s->plane_bytes_state();
+    s->off_kappa = off;
+    off += nd * s->plane_bytes_c();
+    s->off_dtab = off;
+    off += align256(nd * 3 * 4);
   }
   s->dev_bytes = off;
 }
@@ -411,6 +428,7 @@ int upload_materials(starmap_solver* s, double t_eval) {
         for (size_t i = 0; i < c.size(); ++i) c[i] -= sl[i];
       }
     }
+    if (const double d = order_damping(s, l)) for (double& v : c) v += d;
     rc = upload_plane(s, dptr(s, s->off_decay + size_t(p) * s->plane_bytes_c()), gx, gy, c.data(), true);
     if (rc) return rc;
   }
@@ -474,6 +492,8 @@ int upload_basis(starmap_solver* s) {
   }
   HIP_TRY(hipMemcpyAsync(dptr(s, s->off_comb), s->comb_tab.data(), s->comb_tab.size() * 4, hipMemcpyHostToDevice,
                          s->stream));
+  HIP_TRY(hipMemcpyAsync(dptr(s, s->off_comb + align256(s->comb_tab.size() * 4)), s->comb_cst.data(),
+                         s->comb_cst.size() * 8, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->basis_ready = true;
   s->static_done = false;
@@ -497,6 +517,7 @@ int combine_materials(starmap_solver* s, double t_eval) {
   c.basis = dptr(s, s->off_basis);
   c.first = tab + s->tab_first;
   c.entries = tab + s->tab_entries;
+  c.cst = reinterpret_cast<const double*>(dptr(s, s->off_comb + align256(s->comb_tab.size() * 4)));
   c.plane_stride = s->plane_stride;
   const int w = s->static_done ? 1 : 0;
   if (s->nlist[w]) {  // decay planes, compute type
@@ -520,6 +541,54 @@ int combine_materials(starmap_solver* s, double t_eval) {
 int ensure_materials(starmap_solver* s, double t_eval) {
   if (s->separable && !s->time_dependent) return combine_materials(s, t_eval);
   return upload_materials(s, t_eval);
+}
+
+// D_N: kappa on the grid of every order-N moment (compute type), the plane
+// table, and the stability check of the explicit diffusion step.
+int upload_diffusion(starmap_solver* s) {
+  std::vector<int32_t> tab;
+  const double lim = s->dt * (2.0 / (s->dx * s->dx) + 2.0 / (s->dy * s->dy));
+  int j = 0;
+  for (int k = 0; k < s->nmom; ++k) {
+    if (s->moms[k].l != s->N) continue;
+    const int gx = s->moms[k].gx, gy = s->moms[k].gy;
+    std::vector<double> v;
+    int rc = sample(s, s->diffusion, gx, gy, 0.0, v);
+    if (rc) return rc;
+    for (double x : v) {
+      if (!(x >= 0.0) || !std::isfinite(x)) return fail(STARMAP_EINVAL, "diffusion coefficient must be finite and >= 0");
+      if (x * lim > 1.0) return fail(STARMAP_EINVAL, "diffusion step unstable: kappa dt (2/dx^2 + 2/dy^2) > 1");
+    }
+    rc = upload_plane(s, dptr(s, s->off_kappa + size_t(j) * s->plane_bytes_c()), gx, gy, v.data(), true);
+    if (rc) return rc;
+    tab.insert(tab.end(), {k, gx, gy});
+    ++j;
+  }
+  HIP_TRY(hipMemcpyAsync(dptr(s, s->off_dtab), tab.data(), tab.size() * 4, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->diffusion_ready = true;
+  return STARMAP_OK;
+}
+
+// D_tau on the order-N moments.
+int diffuse(starmap_solver* s, double tau) {
+  DiffusionArgs a;
+  a.u = dptr(s, s->off_state);
+  a.tmp = dptr(s, s->off_dtmp);
+  a.kappa = dptr(s, s->off_kappa);
+  a.tab = reinterpret_cast<const int*>(dptr(s, s->off_dtab));
+  a.plane_stride = s->plane_stride;
+  a.pitch = s->pitch;
+  a.nx = s->nx;
+  a.ny = s->ny;
+  a.px = s->px;
+  a.py = s->py;
+  a.nplanes = s->N + 1;
+  a.rdx2 = 1.0 / (s->dx * s->dx);
+  a.rdy2 = 1.0 / (s->dy * s->dy);
+  a.tau = tau;
+  HIP_TRY(launch_diffusion(s->storage, a, (s->nx + 1) * (s->ny + 1), s->stream));
+  return STARMAP_OK;
 }
 
 // initial state planes (zero where no initial field is set)
@@ -552,6 +621,10 @@ int ensure_device(starmap_solver* s) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   rc = upload_initial(s);
   if (rc) return rc;
+  if (s->has_diffusion) {
+    rc = upload_diffusion(s);
+    if (rc) return rc;
+  }
   // diagnostics geometry: valid points per plane
   {
     std::vector<int32_t> geo(size_t(s->nmom) * 2);
@@ -887,6 +960,42 @@ int starmap_add_field_term(starmap_solver* s, int32_t which, int32_t index, star
   return STARMAP_OK;
 }
 
+int starmap_set_filter_damping(starmap_solver* s, const double* damping) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (damping) {
+    for (int l = 0; l <= s->N; ++l)
+      if (!(damping[l] >= 0.0) || !std::isfinite(damping[l]))
+        return fail(STARMAP_EINVAL, "filter damping must be finite and >= 0");
+    if (s->device_ready && !s->anisotropic)
+      return fail(STARMAP_ESTATE, "filter damping must first be set before the first device call");
+    s->damping.assign(damping, damping + s->N + 1);
+  } else {
+    s->damping.clear();
+  }
+  if (!s->device_ready) {
+    if (damping) s->anisotropic = true;  // per-order decay planes
+    layout(s);
+  } else if (s->separable) {
+    // the decay outputs come first in the combination table, in plane order
+    for (int p = 0; p < s->dmap.nplanes; ++p) s->comb_cst[size_t(p)] = order_damping(s, s->dmap.plane_l[p]);
+    s->basis_ready = false;
+  }
+  s->materials_ready = false;
+  return STARMAP_OK;
+}
+
+int starmap_set_diffusion(starmap_solver* s, starmap_field_fn kappa, void* ctx) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (s->device_ready) return fail(STARMAP_ESTATE, "the D_N diffusion must be set before the first device call");
+  if (kappa && s->closure) return fail(STARMAP_EINVAL, "the learned closure and D_N do not combine");
+  s->diffusion = FieldSource{};
+  s->diffusion.fn = kappa;
+  s->diffusion.ctx = ctx;
+  s->has_diffusion = kappa != nullptr;
+  layout(s);
+  return STARMAP_OK;
+}
+
 int starmap_set_initial(starmap_solver* s, int32_t k, starmap_field_fn f, void* ctx) {
   if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
   int rc = check_k(s, k);
@@ -982,9 +1091,18 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
   if (nsteps == 0) return STARMAP_OK;
   if (s->closure && (s->time_dependent || s->separable))
     return fail(STARMAP_EINVAL, "the learned closure needs time-independent data");
+  if (s->closure && s->has_diffusion) return fail(STARMAP_EINVAL, "the learned closure and D_N do not combine");
   int rc = ensure_device(s);
   if (rc) return rc;
   const double dt = s->dt;
+  // the even part of a step: S^e_dt, or S^e_{dt/2} D_dt S^e_{dt/2} with the D_N diffusion step
+  auto even = [&]() -> int {
+    if (!s->has_diffusion) return sweep(s, 0, dt);
+    int r = sweep(s, 0, 0.5 * dt);
+    if (!r) r = diffuse(s, dt);
+    if (!r) r = sweep(s, 0, 0.5 * dt);
+    return r;
+  };
   if (!s->time_dependent && !s->separable) {
     if (!s->materials_ready) {
       rc = upload_materials(s, s->t + 0.5 * dt);
@@ -993,7 +1111,7 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
     rc = sweep(s, 1, 0.5 * dt);
     if (rc) return rc;
     for (int64_t i = 0; i < nsteps; ++i) {
-      rc = sweep(s, 0, dt);
+      rc = even();
       if (rc) return rc;
       rc = sweep(s, 1, i + 1 < nsteps ? dt : 0.5 * dt);
       if (rc) return rc;
@@ -1005,7 +1123,7 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
       if (rc) return rc;
       rc = sweep(s, 1, 0.5 * dt);
       if (rc) return rc;
-      rc = sweep(s, 0, dt);
+      rc = even();
       if (rc) return rc;
       rc = sweep(s, 1, 0.5 * dt);
       if (rc) return rc;
@@ -1017,7 +1135,7 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
       if (rc) return rc;
       rc = sweep(s, 1, 0.5 * dt);
       if (rc) return rc;
-      rc = sweep(s, 0, dt);
+      rc = even();
       if (rc) return rc;
       rc = sweep(s, 1, 0.5 * dt);
       if (rc) return rc;
@@ -1545,6 +1663,7 @@ int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_
     if (!v[i]) return fail(STARMAP_EINVAL, "NULL solver in batch");
     if (v[i]->time_dependent || v[i]->separable)
       return fail(STARMAP_EINVAL, "batched solvers need time-independent data");
+    if (v[i]->has_diffusion) return fail(STARMAP_EINVAL, "batched solvers cannot take the D_N diffusion step");
     if (v[i]->closure) return fail(STARMAP_EINVAL, "closure solvers are not batched");
     if (v[i]->storage != v[0]->storage) return fail(STARMAP_EINVAL, "batched solvers need one storage precision");
   }

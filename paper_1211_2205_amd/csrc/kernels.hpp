@@ -73,14 +73,15 @@ hipError_t launch_sweep_batch(int storage, int variant, const BatchEntry* table,
 
 // Linear combination of basis planes (compute type) into decay planes
 // (compute type) or source planes (storage type).  For each pair (o, d) of
-// list: plane d of out = sum over entries e in [first[o], first[o+1]) of
-// sign_e * factor_e * basis[b_e], where entries holds (b_e, term_e, sign_e)
+// list: plane d of out = cst[o] + sum over entries e in [first[o], first[o+1])
+// of sign_e * factor_e * basis[b_e], where entries holds (b_e, term_e, sign_e)
 // and factor_e = a[term_e] (or 1 when term_e < 0).
 constexpr int COMBINE_MAX_TERMS = 32;
 struct CombineArgs {
   const void* basis;
   const int* first;
   const int* entries;
+  const double* cst;  // per output: constant added to the sum
   const int* list;
   void* out;
   int64_t plane_stride;
@@ -88,6 +89,22 @@ struct CombineArgs {
   double a[COMBINE_MAX_TERMS];
 };
 hipError_t launch_combine(int storage, bool to_compute_type, const CombineArgs& a, hipStream_t stream);
+
+// Diffusion step of the D_N model on the order-N moments (j = 0..nplanes-1):
+// tmp[j] = u_k + tau kappa_j (second difference along x * rdx2 + along y *
+// rdy2) at every point of moment k's grid (tab[3j] = k, tab[3j+1] = gx,
+// tab[3j+2] = gy), with the staging index map at the boundary; then the
+// copy kernel writes tmp[j] back to plane k.
+struct DiffusionArgs {
+  void* u;            // state planes, storage type
+  void* tmp;          // nplanes scratch planes, storage type
+  const void* kappa;  // nplanes planes, compute type
+  const int* tab;
+  int64_t plane_stride;
+  int pitch, nx, ny, px, py, nplanes;
+  double rdx2, rdy2, tau;
+};
+hipError_t launch_diffusion(int storage, const DiffusionArgs& a, int max_points, hipStream_t stream);
 
 // FP64 diagnostics of a state: mass of plane 0 (times cell area is applied on
 // the host), sum of squares and max |u| over all valid points, count of

@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(kThreads) combine_kernel(CombineArgs a) {
   const int64_t base = int64_t(blockIdx.x) * (kThreads * kPerThread) + threadIdx.x;
   C acc[kPerThread];
 #pragma unroll
-  for (int r = 0; r < kPerThread; ++r) acc[r] = C(0);
+  for (int r = 0; r < kPerThread; ++r) acc[r] = C(a.cst[o]);
   for (int e = e0; e < e1; ++e) {
     const int b = a.entries[3 * e], term = a.entries[3 * e + 1], sign = a.entries[3 * e + 2];
     const C coef = C(double(sign) * (term >= 0 ? a.a[term] : 1.0));

@@ -76,6 +76,13 @@ struct starmap_solver {
   std::map<int, starmap::detail::FieldSource> source;            // k -> q_k
   std::map<int, starmap::detail::FieldSource> initial;           // k -> u_k(0)
   bool anisotropic = false;
+  // filtered P_N: damping added to the decay of each order (empty: none)
+  std::vector<double> damping;
+  // diffusion-corrected P_N: kappa of the diffusion step on the order-N moments
+  starmap::detail::FieldSource diffusion;
+  bool has_diffusion = false;
+  size_t off_dtmp = 0, off_kappa = 0, off_dtab = 0;  // scratch planes, kappa planes, plane table
+  bool diffusion_ready = false;
   bool time_dependent = false;
 
   starmap::DecayMap dmap;
@@ -133,6 +140,7 @@ struct starmap_solver {
   std::vector<Basis> basis;
   std::vector<starmap::detail::FieldTerm> time_terms;
   std::vector<int32_t> comb_tab;
+  std::vector<double> comb_cst;  // per output: constant term (filter damping of decay planes)
   int tab_first = 0, tab_entries = 0, tab_list[4] = {}, nlist[4] = {};
   bool basis_ready = false, static_done = false;
 

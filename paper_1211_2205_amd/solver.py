@@ -169,6 +169,10 @@ class Solver:
                     s.set_source(k, (lambda c: (lambda t, x, y: c * prob.beam_profile(t, x, y)))(float(w[k])), td)
         for k, f in prob.initial.items():
             s.set_initial(k, f)
+        if getattr(prob, "filter_damping", None) is not None:
+            s.set_filter_damping(prob.filter_damping)
+        if getattr(prob, "diffusion", None) is not None:
+            s.set_diffusion(prob.diffusion)
         return s
 
     # ----------------------------------------------------------- fields
@@ -193,6 +197,23 @@ class Solver:
         B.check(B.lib().starmap_add_field_term(self._h, _TERM_FIELD[which], int(index),
                                                _field_callback(lambda t, x, y: g(x, y), self._keep), None,
                                                _time_callback(a, self._keep), None))
+
+    def set_filter_damping(self, damping):
+        """Filtered P_N: damping[l] (l = 0..N) added to the decay of every
+        order-l moment; None removes it."""
+        if damping is None:
+            B.check(B.lib().starmap_set_filter_damping(self._h, None))
+            return
+        d = np.ascontiguousarray(damping, dtype=np.float64)
+        if d.shape != (self.N + 1,):
+            raise ValueError(f"filter damping needs N + 1 = {self.N + 1} values")
+        B.check(B.lib().starmap_set_filter_damping(self._h, d.ctypes.data_as(B._dp)))
+
+    def set_diffusion(self, kappa):
+        """Diffusion-corrected P_N: kappa(t, x, y) of the diffusion step on the
+        order-N moments (sampled once); None removes it."""
+        cb = _field_callback(kappa, self._keep) if kappa is not None else B.FIELD_FN()
+        B.check(B.lib().starmap_set_diffusion(self._h, cb, None))
 
     def set_initial(self, k, f):
         B.check(B.lib().starmap_set_initial(self._h, int(k), _field_callback(f, self._keep), None))

@@ -177,3 +177,27 @@ def test_tile_variants_are_enumerable():
         s.set_variant(v)  # P_3 fits every tile within the 64 KiB assumed without a device
     with pytest.raises(pa.StarmapError, match="unknown variant"):
         s.set_variant(n)
+
+
+def test_fpn_and_dn_settings_are_validated_on_the_host():
+    s = pa.Solver(4, (12, 12), (0, 1, 0, 1))
+    base = s.workspace_bytes()
+    with pytest.raises(ValueError):
+        s.set_filter_damping([0.0] * 4)
+    with pytest.raises(pa.StarmapError):
+        s.set_filter_damping([0.0, 1.0, -1.0, 0.0, 0.0])
+    with pytest.raises(pa.StarmapError):
+        s.set_filter_damping([0.0, 1.0, float("nan"), 0.0, 0.0])
+    s.set_filter_damping(wl.filter_damping(4, 3.0))
+    # per-order decay planes: more device memory
+    assert s.workspace_bytes() > base
+    s.set_filter_damping(None)
+    d0 = s.workspace_bytes()
+    s.set_diffusion(lambda t, x, y: 0.001 + 0 * x)
+    # scratch and kappa planes for the N + 1 order-N moments
+    assert s.workspace_bytes() > d0
+    s.set_diffusion(None)
+    assert s.workspace_bytes() == d0
+    c = pa.Solver(5, (12, 12), (0, 1, 0, 1), closure="learned")
+    with pytest.raises(pa.StarmapError):
+        c.set_diffusion(lambda t, x, y: 0.001 + 0 * x)
