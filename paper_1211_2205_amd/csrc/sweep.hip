@@ -46,6 +46,18 @@ __device__ __forceinline__ void store_stream(bf16* p, bf16 v) {
   __builtin_nontemporal_store(v.bits, reinterpret_cast<uint16_t*>(p));
 }
 
+// Element at a 32-bit byte offset from a wave-uniform base: the address is
+// base + zero-extended offset, which the compiler issues as a global access
+// with a scalar base and one VGPR offset (no 64-bit address arithmetic).
+template <typename T>
+__device__ __forceinline__ T* at(T* base, uint32_t byte_off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t byte_off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // Output rows are read once per sweep, just before they are overwritten.
 __device__ __forceinline__ float load_stream(const float* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ double load_stream(const double* p) { return __builtin_nontemporal_load(p); }
@@ -93,8 +105,13 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   // t < TY + TX, one halo point: of the halo column read by x differences
   // (lx = 0 or TX) or of the halo row read by y differences (ly = 0 or TY);
   // the corners are never read.  Source and LDS offsets are affine in (ox, oy):
-  // src = sb + ox * sx + oy * sy, dst = db + ox * ddx + oy * ddy.
-  int sb[EPT], sx[EPT], sy[EPT], db[EPT], ddx[EPT], ddy[EPT];
+  // src = sb + ox * sx + oy * sy, dst = db + ox * ddx + oy * ddy.  ox and oy
+  // are 0 or 1 and uniform, so they enter as masks (no integer multiplies);
+  // source offsets are 32-bit byte offsets from the plane base (sums wrap
+  // modulo 2^32 to the in-plane offset).
+  uint32_t sb[EPT], sx[EPT], sy[EPT];
+  int db[EPT], ddx[EPT], ddy[EPT];
+  constexpr uint32_t TS = sizeof(T);
   bool sv[EPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -102,9 +119,9 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     const int tx = e % TX, ty = e / TX;
     const int xn = map_axis(x0 + tx, a.nx, a.px, 0), xc = map_axis(x0 + tx, a.nx, a.px, 1);
     const int yn = map_axis(y0 + ty, a.ny, a.py, 0), yc = map_axis(y0 + ty, a.ny, a.py, 1);
-    sb[p] = yn * a.pitch + xn;
-    sx[p] = xc - xn;
-    sy[p] = (yc - yn) * a.pitch;
+    sb[p] = uint32_t(yn * a.pitch + xn) * TS;
+    sx[p] = uint32_t(xc - xn) * TS;
+    sy[p] = uint32_t((yc - yn) * a.pitch) * TS;
     db[p] = ty * LW + tx;
     ddx[p] = 1;
     ddy[p] = LW;
@@ -117,9 +134,9 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       const int i = tid;
       const int xn = map_axis(x0 + TX, a.nx, a.px, 0), xc = map_axis(x0 - 1, a.nx, a.px, 1);
       const int yn = map_axis(y0 + i, a.ny, a.py, 0), yc = map_axis(y0 + i, a.ny, a.py, 1);
-      sb[h] = yn * a.pitch + xn;
-      sx[h] = xc - xn;
-      sy[h] = (yc - yn) * a.pitch;
+      sb[h] = uint32_t(yn * a.pitch + xn) * TS;
+      sx[h] = uint32_t(xc - xn) * TS;
+      sy[h] = uint32_t((yc - yn) * a.pitch) * TS;
       db[h] = i * LW + TX;
       ddx[h] = -TX;
       ddy[h] = LW;
@@ -127,9 +144,9 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       const int j = tid < TY + TX ? tid - TY : 0;
       const int xn = map_axis(x0 + j, a.nx, a.px, 0), xc = map_axis(x0 + j, a.nx, a.px, 1);
       const int yn = map_axis(y0 + TY, a.ny, a.py, 0), yc = map_axis(y0 - 1, a.ny, a.py, 1);
-      sb[h] = yn * a.pitch + xn;
-      sx[h] = xc - xn;
-      sy[h] = (yc - yn) * a.pitch;
+      sb[h] = uint32_t(yn * a.pitch + xn) * TS;
+      sx[h] = uint32_t(xc - xn) * TS;
+      sy[h] = uint32_t((yc - yn) * a.pitch) * TS;
       db[h] = TY * LW + j;
       ddx[h] = 1;
       ddy[h] = -TY * LW;
@@ -138,7 +155,8 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 
   // my output points: LDS position, plane offset, and whether the point exists
   // on each of the sweep's two output grids
-  int pos[PPT], goff[PPT];
+  int pos[PPT];
+  uint32_t goff[PPT];  // element offset in a plane
   bool val0[PPT], val1[PPT];
   {
     // even sweep: slot 0 = G11 (cell, cell), slot 1 = G22 (node, node);
@@ -152,7 +170,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       const int tx = e % TX, ty = e / TX;
       const int X = x0 + tx, Y = y0 + ty;
       pos[p] = ty * LW + tx;
-      goff[p] = Y * a.pitch + X;
+      goff[p] = uint32_t(Y * a.pitch + X);
       val0[p] = X < vx0 && Y < vy0;
       val1[p] = X < vx1 && Y < vy1;
     }
@@ -169,7 +187,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
           const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
-            if (sv[q]) v[b][q] = src[sb[q] + ld.z * sx[q] + ld.w * sy[q]];
+            if (sv[q]) v[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
         }
       }
 #pragma unroll
@@ -178,7 +196,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
           const int4 ld = loads[first + bb + b];
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
-            if (sv[q]) L[ld.y + db[q] + ld.z * ddx[q] + ld.w * ddy[q]] = v[b][q];
+            if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = v[b][q];
         }
       }
     }
@@ -194,7 +212,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const T* up = U + int64_t(rec[0]) * a.plane_stride;
         const bool s1 = rec[1] != 0;
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(load_stream(&up[goff[p]])) : C(0);
+        for (int p = 0; p < PPT; ++p) uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(load_stream(at(up, goff[p] * TS))) : C(0);
       }
     }
   };
@@ -228,7 +246,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
-          if (sv[q]) stg[b][q] = src[sb[q] + ld.z * sx[q] + ld.w * sy[q]];
+          if (sv[q]) stg[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
       }
     }
     // 2. the first output rows of the next order
@@ -250,7 +268,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
               const bool v = gslot ? val1[p] : val0[p];
-              const C c = v ? dp[goff[p]] : C(0);
+              const C c = v ? *at(dp, goff[p] * uint32_t(sizeof(C))) : C(0);
               const C E = expm1div(-c * a.tau);
               if (gslot == 0) { c0[p] = c; e0[p] = E; } else { c1[p] = c; e1[p] = E; }
             }
@@ -276,7 +294,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
               const C c = gslot ? c1[p] : c0[p];
               const C E = gslot ? e1[p] : e0[p];
               const C u = ua[i][p];
-              store_stream(&up[goff[p]], from_c<T>(u + a.tau * (W - c * u) * E));
+              store_stream(at(up, goff[p] * TS), from_c<T>(u + a.tau * (W - c * u) * E));
             }
           }
         }
@@ -290,7 +308,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const int4 ld = loads[nxt.x + b];
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
-          if (sv[q]) L[ld.y + db[q] + ld.z * ddx[q] + ld.w * ddy[q]] = stg[b][q];
+          if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = stg[b][q];
       }
     }
     if (nl > MAXP) stage_sync(nxt.x, MAXP, nl);
