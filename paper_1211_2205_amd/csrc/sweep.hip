@@ -65,6 +65,10 @@ __device__ __forceinline__ bf16 load_stream(const bf16* p) {
   return bf16{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
 }
 
+// s_waitcnt immediate for vmcnt(0) with the other counters left alone
+// (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int kWaitVm0 = 0x0F70;
+
 // Body of one workgroup's work in a sweep: spatial tile and m range number lb
 // (lb = tile * nchunks + range) of one instance.
 template <typename T, int TX, int TY, int CAP>
@@ -187,7 +191,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
           const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
-            if (sv[q]) v[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
+            v[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
         }
       }
 #pragma unroll
@@ -226,6 +230,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     stage_sync(ord.x, 0, ord.y - ord.x);
     load_rows(ua, ord.z + grp, ord.w);
   }
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);  // see the end of the order loop
   __syncthreads();
 
   // decay cache per output grid of the sweep: (plane id, c, E(-c tau))
@@ -246,7 +251,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
-          if (sv[q]) stg[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
+          stg[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
       }
     }
     // 2. the first output rows of the next order
@@ -254,7 +259,10 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     if (has_next) load_rows(ub, nxt.z + grp, nxt.w);
     // 3. update this order's rows from the current window
     for (int r0 = ord.z + grp; r0 < ord.w; r0 += NG * RB) {
-      if (r0 != ord.z + grp) load_rows(ua, r0, ord.w);
+      if (r0 != ord.z + grp) {  // more rows than the registers hold: load the next batch now
+        load_rows(ua, r0, ord.w);
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      }
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
@@ -312,6 +320,12 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       }
     }
     if (nl > MAXP) stage_sync(nxt.x, MAXP, nl);
+    // Every load of this order has been consumed: wait for all of them here.
+    // The compiler cannot match the conditional loads with their conditional
+    // uses, so without this wait it assumes the window registers may still be
+    // receiving and waits for every outstanding load at their first reuse,
+    // which would stall the next order's prefetch right after it is issued.
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RB; ++i)
