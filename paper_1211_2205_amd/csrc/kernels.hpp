@@ -31,8 +31,7 @@ struct SweepArgs {
 
 struct TileShape {
   int tx, ty;
-  int cap;    // planes of one staged order and output rows per order held in registers
-  int depth;  // orders of look-ahead of the register staging (1 or 2)
+  int cap;  // planes of one staged order and output rows per order held in registers
 };
 
 // Tile shapes compiled into the library (index = variant id).
