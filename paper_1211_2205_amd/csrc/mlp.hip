@@ -377,6 +377,14 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
       const int yn = min(max(j + a - 1, 0), G.ny - G.py);
       rowy[1][a] = (G.py ? (yn + 1 == G.ny ? 0 : yn + 1) : yn) * G.pitch;
     }
+    // the material inputs of this point (wave 3), loaded now so that they
+    // arrive with the stencil
+    C sig_a = C(0), sig_t = C(0);
+    if (w == 3) {
+      const int64_t o = int64_t(min(j, G.ny - 1)) * G.pitch + min(i, G.nx - 1);
+      sig_a = decay[int64_t(G.dk_a) * G.plane_stride + o];
+      sig_t = decay[int64_t(G.dk_t) * G.plane_stride + o];
+    }
     // two passes over the stencil (the second re-reads cached values): the
     // sum of squares, then the normalised inputs
     C ss = C(0);
@@ -393,27 +401,38 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
         }
       }
     }
+    // the second pass's first plane (every wave has one) is re-read while the
+    // norm is reduced across the waves
+    C v0[9];
+    {
+      const T* up = U + int64_t(G.k[w]) * G.plane_stride;
+      const int cx = G.nodex[w], cy = G.nodey[w];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v0[q] = to_c(up[rowy[cy][q / 3] + colx[cx][q % 3]]);
+    }
     __syncthreads();  // the previous block's reads of Xa, nu_s and part are done
     part[w * CB + lane] = ss;
     __syncthreads();
     const C nu = sqrt(((part[lane] + part[CB + lane]) + part[2 * CB + lane]) + part[3 * CB + lane]) + C(CLOSURE_EPS);
     const C rnu = C(1) / nu;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
+    for (int q = 0; q < 9; ++q) Xa[lane * LDW + 9 * w + q] = uint16_t(bf16_in(v0[q] * rnu));
+#pragma unroll
+    for (int t = 1; t < 3; ++t) {
       const int p = w + 4 * t;
       if (p < CLOSURE_PLANES) {
         const T* up = U + int64_t(G.k[p]) * G.plane_stride;
         const int cx = G.nodex[p], cy = G.nodey[p];
+        // all nine loads first, so they are in flight together
+        C v[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const C v = to_c(up[rowy[cy][q / 3] + colx[cx][q % 3]]);
-          Xa[lane * LDW + 9 * p + q] = uint16_t(bf16_in(v * rnu));
-        }
+        for (int q = 0; q < 9; ++q) v[q] = to_c(up[rowy[cy][q / 3] + colx[cx][q % 3]]);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Xa[lane * LDW + 9 * p + q] = uint16_t(bf16_in(v[q] * rnu));
       }
     }
     if (w == 3) {
-      C fa, fs;
-      sigma_inputs(decay, G, i, j, &fa, &fs);
+      const C fa = log10(sig_a + C(0.01)), fs = log10((sig_t - sig_a) + C(0.01));
       Xa[lane * LDW + 99] = uint16_t(bf16_bits(fa));
       Xa[lane * LDW + 100] = uint16_t(bf16_bits(fs));
       for (int q = 101; q < CLOSURE_IN; ++q) Xa[lane * LDW + q] = 0;

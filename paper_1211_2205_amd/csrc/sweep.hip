@@ -221,6 +221,53 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     }
   };
 
+  // decay cache per output grid of the sweep: (plane id, c, E(-c tau))
+  int cdk0 = -1, cdk1 = -1;
+  C c0[PPT], e0[PPT], c1[PPT], e1[PPT];
+  // The decay planes an order needs (one per output grid; they change with
+  // the order when scattering or filtering is anisotropic) are loaded with
+  // that order's window, so no load waits inside the compute.
+  int ndk0 = -1, ndk1 = -1;
+  C nc0[PPT], nc1[PPT];
+  auto prefetch_decay = [&](const int4 od, C (&n0)[PPT], C (&n1)[PPT]) {
+    // every row of an order shares the decay plane of its output grid
+    ndk0 = -1;
+    ndk1 = -1;
+    for (int r = od.z + grp; r < od.w && (ndk0 < 0 || ndk1 < 0); r += NG) {
+      const int gs = rows[16 * r + 1], dk = rows[16 * r + 2];
+      // value selects (a conditional store to one of two variables would be
+      // merged into a store through a selected address, i.e. stack memory)
+      ndk0 = (gs == 0 && ndk0 < 0) ? dk : ndk0;
+      ndk1 = (gs != 0 && ndk1 < 0) ? dk : ndk1;
+    }
+    const bool l0 = ndk0 >= 0 && ndk0 != cdk0, l1 = ndk1 >= 0 && ndk1 != cdk1;
+    const C* d0 = decay + int64_t(l0 ? ndk0 : 0) * a.plane_stride;
+    const C* d1 = decay + int64_t(l1 ? ndk1 : 0) * a.plane_stride;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      if (l0) n0[p] = val0[p] ? *at(d0, goff[p] * uint32_t(sizeof(C))) : C(0);
+      if (l1) n1[p] = val1[p] ? *at(d1, goff[p] * uint32_t(sizeof(C))) : C(0);
+    }
+  };
+  auto apply_decay = [&]() {
+    if (ndk0 >= 0 && ndk0 != cdk0) {
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        c0[p] = nc0[p];
+        e0[p] = expm1div(-nc0[p] * a.tau);
+      }
+      cdk0 = ndk0;
+    }
+    if (ndk1 >= 0 && ndk1 != cdk1) {
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        c1[p] = nc1[p];
+        e1[p] = expm1div(-nc1[p] * a.tau);
+      }
+      cdk1 = ndk1;
+    }
+  };
+
   // the padding couplings read this plane of zeros
   for (int e = tid; e < P; e += 256) L[a.zero_off + e] = from_c<T>(C(0));
   // prologue: the first window and the first rows
@@ -229,16 +276,14 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     const int4 ord = orders[chk.x];
     stage_sync(ord.x, 0, ord.y - ord.x);
     load_rows(ua, ord.z + grp, ord.w);
+    prefetch_decay(ord, nc0, nc1);
   }
   __builtin_amdgcn_s_waitcnt(kWaitVm0);  // see the end of the order loop
   __syncthreads();
 
-  // decay cache per output grid of the sweep: (plane id, c, E(-c tau))
-  int cdk0 = -1, cdk1 = -1;
-  C c0[PPT], e0[PPT], c1[PPT], e1[PPT];
-
   for (int o = chk.x; o < chk.y; ++o) {
     const int4 ord = orders[o];
+    apply_decay();
     const bool has_next = o + 1 < chk.y;
     const int4 nxt = has_next ? orders[o + 1] : make_int4(0, 0, 0, 0);
     const int nl = nxt.y - nxt.x;
@@ -256,7 +301,10 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     }
     // 2. the first output rows of the next order
     C ub[RB][PPT];
-    if (has_next) load_rows(ub, nxt.z + grp, nxt.w);
+    if (has_next) {
+      load_rows(ub, nxt.z + grp, nxt.w);
+      prefetch_decay(nxt, nc0, nc1);
+    }
     // 3. update this order's rows from the current window
     for (int r0 = ord.z + grp; r0 < ord.w; r0 += NG * RB) {
       if (r0 != ord.z + grp) {  // more rows than the registers hold: load the next batch now
@@ -269,19 +317,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         if (r < ord.w) {
           const int* rec = rows + 16 * r;
           const C* cf = rcoef + 8 * r;
-          const int k = rec[0], gslot = rec[1], dk = rec[2], so = rec[3];
-    // refresh the decay cache of this output grid if the plane changed
-          if (gslot == 0 ? (dk != cdk0) : (dk != cdk1)) {
-            const C* dp = decay + int64_t(dk) * a.plane_stride;
-#pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-              const bool v = gslot ? val1[p] : val0[p];
-              const C c = v ? *at(dp, goff[p] * uint32_t(sizeof(C))) : C(0);
-              const C E = expm1div(-c * a.tau);
-              if (gslot == 0) { c0[p] = c; e0[p] = E; } else { c1[p] = c; e1[p] = E; }
-            }
-            if (gslot == 0) cdk0 = dk; else cdk1 = dk;
-          }
+          const int k = rec[0], gslot = rec[1], so = rec[3];
           T* up = U + int64_t(k) * a.plane_stride;
 #pragma unroll
           for (int p = 0; p < PPT; ++p) {
