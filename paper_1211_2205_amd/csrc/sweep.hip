@@ -69,13 +69,24 @@ __device__ __forceinline__ bf16 load_stream(const bf16* p) {
 // (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
 
+// The sweep programs (m ranges, orders, staging loads, rows, coefficients) are
+// read-only during a launch and read at wave-uniform addresses: held as
+// constant-address-space pointers, those reads are scalar loads wherever the
+// pointer comes from (a kernel argument or an instance table in memory).
+template <typename P>
+using cptr = __attribute__((address_space(4))) const P*;
+
+// Entry i of a table of int4 records.
+__device__ __forceinline__ int4 rec4(cptr<int> t, int i) {
+  return make_int4(t[4 * i], t[4 * i + 1], t[4 * i + 2], t[4 * i + 3]);
+}
+
 // Body of one workgroup's work in a sweep: spatial tile and m range number lb
 // (lb = tile * nchunks + range) of one instance.
 template <typename T, int TX, int TY, int CAP>
 __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
-                                           const int4* __restrict__ chunks, const int4* __restrict__ orders,
-                                           const int4* __restrict__ loads, const int* __restrict__ rows,
-                                           const typename ComputeOf<T>::type* __restrict__ rcoef,
+                                           cptr<int> chunks, cptr<int> orders, cptr<int> loads, cptr<int> rows,
+                                           cptr<typename ComputeOf<T>::type> rcoef,
                                            const SweepScalars<typename ComputeOf<T>::type>& a, const int lb) {
   using C = typename ComputeOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -96,7 +107,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 
   const int tid = threadIdx.x;
   const int tile = lb / a.nchunks;
-  const int4 chk = chunks[lb - tile * a.nchunks];
+  const int4 chk = rec4(chunks, lb - tile * a.nchunks);
   if (chk.x >= chk.y) return;  // no output rows in this m range
   const int x0 = (tile % a.ntx) * TX;
   const int y0 = (tile / a.ntx) * TY;
@@ -187,7 +198,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
       for (int b = 0; b < LB; ++b) {
         if (bb + b < b1) {
-          const int4 ld = loads[first + bb + b];
+          const int4 ld = rec4(loads, first + bb + b);
           const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
@@ -197,7 +208,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
       for (int b = 0; b < LB; ++b) {
         if (bb + b < b1) {
-          const int4 ld = loads[first + bb + b];
+          const int4 ld = rec4(loads, first + bb + b);
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
             if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = v[b][q];
@@ -212,7 +223,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     for (int i = 0; i < RB; ++i) {
       const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
       if (r < r1) {
-        const int* rec = rows + 16 * r;
+        cptr<int> rec = rows + 16 * r;
         const T* up = U + int64_t(rec[0]) * a.plane_stride;
         const bool s1 = rec[1] != 0;
 #pragma unroll
@@ -273,7 +284,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   // prologue: the first window and the first rows
   C ua[RB][PPT];
   {
-    const int4 ord = orders[chk.x];
+    const int4 ord = rec4(orders, chk.x);
     stage_sync(ord.x, 0, ord.y - ord.x);
     load_rows(ua, ord.z + grp, ord.w);
     prefetch_decay(ord, nc0, nc1);
@@ -282,17 +293,17 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   __syncthreads();
 
   for (int o = chk.x; o < chk.y; ++o) {
-    const int4 ord = orders[o];
+    const int4 ord = rec4(orders, o);
     apply_decay();
     const bool has_next = o + 1 < chk.y;
-    const int4 nxt = has_next ? orders[o + 1] : make_int4(0, 0, 0, 0);
+    const int4 nxt = has_next ? rec4(orders, o + 1) : make_int4(0, 0, 0, 0);
     const int nl = nxt.y - nxt.x;
     // 1. the next window into registers (every thread loads its own elements)
     T stg[MAXP][EPT];
 #pragma unroll
     for (int b = 0; b < MAXP; ++b) {
       if (b < nl) {
-        const int4 ld = loads[nxt.x + b];
+        const int4 ld = rec4(loads, nxt.x + b);
         const T* src = U + int64_t(ld.x) * a.plane_stride;
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
@@ -315,8 +326,8 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       for (int i = 0; i < RB; ++i) {
         const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
         if (r < ord.w) {
-          const int* rec = rows + 16 * r;
-          const C* cf = rcoef + 8 * r;
+          cptr<int> rec = rows + 16 * r;
+          cptr<C> cf = rcoef + 8 * r;
           const int k = rec[0], gslot = rec[1], so = rec[3];
           T* up = U + int64_t(k) * a.plane_stride;
 #pragma unroll
@@ -349,7 +360,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
     for (int b = 0; b < MAXP; ++b) {
       if (b < nl) {
-        const int4 ld = loads[nxt.x + b];
+        const int4 ld = rec4(loads, nxt.x + b);
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
           if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = stg[b][q];
@@ -379,7 +390,9 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
              const SweepScalars<typename ComputeOf<T>::type> a) {
   // logical block = tile * nchunks + chunk: the m ranges of one tile run on
   // the same XCD, one after another, and share its L2
-  sweep_tile<T, TX, TY, CAP>(U, decay, chunks, orders, loads, rows, rcoef, a, xcd_tile(blockIdx.x, gridDim.x));
+  using C = typename ComputeOf<T>::type;
+  sweep_tile<T, TX, TY, CAP>(U, decay, (cptr<int>)chunks, (cptr<int>)orders, (cptr<int>)loads, (cptr<int>)rows,
+                             (cptr<C>)rcoef, a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Sweep number j of a batched run.  Instances are sorted by their number of
@@ -437,9 +450,9 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
   a.zero_off = e.zero_off[par];
   a.parity = par;
   a.tau = C((j == 0 || j == e.nsweeps - 1) ? e.tau_half : e.tau_full);
-  sweep_tile<T, TX, TY, CAP>((T*)(gptr<T>)e.u, (const C*)(gptr<const C>)e.decay, (const int4*)e.chunks[par],
-                             (const int4*)e.orders[par], (const int4*)e.loads[par], (const int*)e.rows[par],
-                             (const C*)(gptr<const C>)e.rcoef[par], a, item - first[lo]);
+  sweep_tile<T, TX, TY, CAP>((T*)(gptr<T>)e.u, (const C*)(gptr<const C>)e.decay, (cptr<int>)e.chunks[par],
+                             (cptr<int>)e.orders[par], (cptr<int>)e.loads[par], (cptr<int>)e.rows[par],
+                             (cptr<C>)e.rcoef[par], a, item - first[lo]);
 }
 
 // ------------------------------------------------------------ variants
