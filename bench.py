@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_line_source_P39_1000_fp32_pmc.json")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_line_source_P39_1000_{}_pmc.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_1211_2205_amd", "csrc", "sweep.hip")
 
 
@@ -40,12 +40,14 @@ def _traffic(launch_bytes, precision):
     """HBM bytes per launch from the committed PMC summary, if it was taken on
     the current sweep kernel source; else None."""
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(PMC_SUMMARY.format(precision)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("sweep_source_sha256_16") != _sweep_source_hash() or rec.get("precision") != precision:
         return None
+    if abs(rec.get("algorithmic_bytes_per_launch", 0.0) - launch_bytes) > 1e-6 * launch_bytes:
+        return None  # counters taken on another workload
     return rec.get("hbm_bytes_per_launch")
 
 

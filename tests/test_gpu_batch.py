@@ -157,3 +157,21 @@ def test_c4_full_batch_sampled_instances(monkeypatch):
         d = s.diagnostics()
         assert d["nonfinite"] == 0 and d["maxabs"] > 0
     b.close()
+
+
+def test_batch_of_filtered_and_anisotropic_instances(monkeypatch):
+    """FP_N damping and anisotropic scattering live in per-order decay planes;
+    a batch of such instances (mixed with plain ones) equals the single runs
+    bitwise and the oracle."""
+    probs = _mixed()[:5]
+    probs[0] = dataclasses.replace(probs[0], filter_damping=wl.filter_damping(probs[0].N, 6.0, power=2))
+    probs[2] = dataclasses.replace(probs[2], filter_damping=wl.filter_damping(probs[2].N, 3.0))
+    probs[3] = dataclasses.replace(probs[3], sigma_sl=lambda l, t, x, y: 0.7 ** l + 0 * x)
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    b.set_variant(6, 6)
+    b.run()
+    for p, s in zip(probs, solvers):
+        assert _identical(s.moments(), _single(p, 6, 6, monkeypatch)), p.name
+        assert rel_l2(s.moments(), run_oracle(p).u) < 1e-12, p.name
+    b.close()
