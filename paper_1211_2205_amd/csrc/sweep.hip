@@ -33,7 +33,7 @@ namespace starmap {
 // scalar cache while the state is written.
 template <typename C>
 struct SweepScalars {
-  int64_t plane_stride;
+  uint32_t ps;  // plane stride in elements
   int pitch, nx, ny, px, py, ntx, nty, nchunks, zero_off, parity;
   C tau;
 };
@@ -76,9 +76,25 @@ constexpr int kWaitVm0 = 0x0F70;
 template <typename P>
 using cptr = __attribute__((address_space(4))) const P*;
 
+// Plane k of an array of planes of ps elements: a 32 x 32 -> 64-bit product
+// (plane strides and plane counts fit 32 bits), cheaper in scalar
+// instructions than a 64-bit multiply.
+template <typename P>
+__device__ __forceinline__ P* plane_at(P* base, int k, uint32_t ps) {
+  return base + uint64_t(uint32_t(k)) * uint64_t(ps);
+}
+
+// Table entry at a 32-bit byte offset (non-negative indices): the scalar load
+// takes the offset as its own operand, with no 64-bit address arithmetic.
+template <typename P>
+__device__ __forceinline__ cptr<P> cat(cptr<P> t, uint32_t byte_off) {
+  return reinterpret_cast<cptr<P>>(reinterpret_cast<cptr<char>>(t) + byte_off);
+}
+
 // Entry i of a table of int4 records.
 __device__ __forceinline__ int4 rec4(cptr<int> t, int i) {
-  return make_int4(t[4 * i], t[4 * i + 1], t[4 * i + 2], t[4 * i + 3]);
+  const cptr<int> q = cat(t, uint32_t(i) * 16u);
+  return make_int4(q[0], q[1], q[2], q[3]);
 }
 
 // Body of one workgroup's work in a sweep: spatial tile and m range number lb
@@ -199,7 +215,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       for (int b = 0; b < LB; ++b) {
         if (bb + b < b1) {
           const int4 ld = rec4(loads, first + bb + b);
-          const T* src = U + int64_t(ld.x) * a.plane_stride;
+          const T* src = plane_at(U, ld.x, a.ps);
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
             v[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
@@ -223,8 +239,8 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     for (int i = 0; i < RB; ++i) {
       const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
       if (r < r1) {
-        cptr<int> rec = rows + 16 * r;
-        const T* up = U + int64_t(rec[0]) * a.plane_stride;
+        cptr<int> rec = cat(rows, uint32_t(r) * 64u);
+        const T* up = plane_at(U, rec[0], a.ps);
         const bool s1 = rec[1] != 0;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(load_stream(at(up, goff[p] * TS))) : C(0);
@@ -245,15 +261,16 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     ndk0 = -1;
     ndk1 = -1;
     for (int r = od.z + grp; r < od.w && (ndk0 < 0 || ndk1 < 0); r += NG) {
-      const int gs = rows[16 * r + 1], dk = rows[16 * r + 2];
+      const cptr<int> rr = cat(rows, uint32_t(r) * 64u);
+      const int gs = rr[1], dk = rr[2];
       // value selects (a conditional store to one of two variables would be
       // merged into a store through a selected address, i.e. stack memory)
       ndk0 = (gs == 0 && ndk0 < 0) ? dk : ndk0;
       ndk1 = (gs != 0 && ndk1 < 0) ? dk : ndk1;
     }
     const bool l0 = ndk0 >= 0 && ndk0 != cdk0, l1 = ndk1 >= 0 && ndk1 != cdk1;
-    const C* d0 = decay + int64_t(l0 ? ndk0 : 0) * a.plane_stride;
-    const C* d1 = decay + int64_t(l1 ? ndk1 : 0) * a.plane_stride;
+    const C* d0 = plane_at(decay, l0 ? ndk0 : 0, a.ps);
+    const C* d1 = plane_at(decay, l1 ? ndk1 : 0, a.ps);
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
       if (l0) n0[p] = val0[p] ? *at(d0, goff[p] * uint32_t(sizeof(C))) : C(0);
@@ -304,7 +321,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     for (int b = 0; b < MAXP; ++b) {
       if (b < nl) {
         const int4 ld = rec4(loads, nxt.x + b);
-        const T* src = U + int64_t(ld.x) * a.plane_stride;
+        const T* src = plane_at(U, ld.x, a.ps);
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
           stg[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
@@ -326,10 +343,10 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       for (int i = 0; i < RB; ++i) {
         const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
         if (r < ord.w) {
-          cptr<int> rec = rows + 16 * r;
-          cptr<C> cf = rcoef + 8 * r;
+          cptr<int> rec = cat(rows, uint32_t(r) * 64u);
+          cptr<C> cf = cat(rcoef, uint32_t(r) * uint32_t(8 * sizeof(C)));
           const int k = rec[0], gslot = rec[1], so = rec[3];
-          T* up = U + int64_t(k) * a.plane_stride;
+          T* up = plane_at(U, k, a.ps);
 #pragma unroll
           for (int p = 0; p < PPT; ++p) {
             C W = C(0);
@@ -438,7 +455,7 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
   const BatchEntryG& e = reinterpret_cast<const BatchEntryG*>(table)[lo];
   const int par = (j & 1) ? 0 : 1;
   SweepScalars<C> a;
-  a.plane_stride = e.plane_stride;
+  a.ps = uint32_t(e.plane_stride);
   a.pitch = e.pitch;
   a.nx = e.nx;
   a.ny = e.ny;
@@ -499,7 +516,7 @@ hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
   hipError_t e = prepare_t<T, TX, TY, CAP>(lds);
   if (e != hipSuccess) return e;
   SweepScalars<C> sc;
-  sc.plane_stride = a.plane_stride;
+  sc.ps = uint32_t(a.plane_stride);
   sc.pitch = a.pitch;
   sc.nx = a.nx;
   sc.ny = a.ny;
