@@ -336,8 +336,19 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
   uint16_t* W3 = Xb + CB * LDW;                      // [16][LDW] output layer, rows >= 6 zero
   C* nu_s = reinterpret_cast<C*>(W3 + 16 * LDW);     // [64]
   C* part = nu_s + CB;                                    // [4][64] partial sums of squares per wave
+  int* otab = reinterpret_cast<int*>(part + 4 * CB);  // [5][8] output plane, extents, nodal flags
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int fk = 8 * (lane >> 4);
+
+  // the output geometry, indexed per lane below, from LDS (indexing the
+  // kernel argument per lane would turn every access into a dependent load)
+  if (tid < 5 * 8) {
+    const int f = tid >> 3, o = tid & 7;
+    int v = 0;
+    if (o < CLOSURE_OUT)
+      v = f == 0 ? G.q[o] : f == 1 ? G.out_nx[o] : f == 2 ? G.out_ny[o] : f == 3 ? G.out_nodex[o] : G.out_nodey[o];
+    otab[tid] = v;
+  }
 
   // this wave's weight fragments: rows 32 w + 16 mi + (lane % 16), k = 32 ks + fk
   const uint4* wv = reinterpret_cast<const uint4*>(net->w);  // rows of CLOSURE_IN / 8 uint4
@@ -493,11 +504,11 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int o = 4 * (lane >> 4) + r;  // output of this lane
-        if (o >= CLOSURE_OUT || pi >= G.out_nx[o] || pj >= G.out_ny[o]) continue;
-        const int X = internal_index(pi, G.out_nodex[o], G.px, G.nx);
-        const int Y = internal_index(pj, G.out_nodey[o], G.py, G.ny);
+        if (o >= CLOSURE_OUT || pi >= otab[8 + o] || pj >= otab[16 + o]) continue;
+        const int X = internal_index(pi, otab[24 + o], G.px, G.nx);
+        const int Y = internal_index(pj, otab[32 + o], G.py, G.ny);
         const C g = nu_s[m] * C(y[r] + b3[r]) / C(G.dx);
-        U[int64_t(G.q[o]) * G.plane_stride + int64_t(Y) * G.pitch + X] = from_c<T>(g);
+        U[int64_t(otab[o]) * G.plane_stride + int64_t(Y) * G.pitch + X] = from_c<T>(g);
       }
     }
   }
@@ -566,7 +577,7 @@ hipError_t launch_closure_samples(int storage, const void* U, const void* decay,
 }
 
 size_t closure_infer_lds_bytes() {
-  return size_t(2 * CB + 16) * LDW * 2 + size_t(5 * CB) * 8;
+  return size_t(2 * CB + 16) * LDW * 2 + size_t(5 * CB) * 8 + 5 * 8 * sizeof(int);
 }
 
 namespace {
