@@ -147,6 +147,47 @@ def models_leg(config, precision, steps):
     return out
 
 
+def fused_leg(N, n, precision, steps):
+    """Parity-fused passes against the separate sweeps on a line source of
+    order N on n x n cells: ms per step for both (autotuned separate sweeps),
+    and the fused pass's algorithmic bandwidth, 2 s bytes per moment and point
+    per step (each moment read and written once)."""
+    import torch
+
+    import paper_1211_2205_amd as pa
+    import workloads as wl
+    out = {"workload": f"line_source_P{N}_{n}_{precision}"}
+    for mode in ("separate", "fused"):
+        prob = wl.line_source(N=N, n=n, s=0.03, precision=precision)
+        prob.t_final = 1.0
+        s = pa.Solver.from_problem(prob)
+        if mode == "fused":
+            s.set_fused(True)
+        s.bind_torch()
+        if mode == "separate":
+            s.autotune(1)
+        s.advance(2)
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(steps)
+        s.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        rec = {"ms_per_step": ms, "value": n * n * s.nmom * steps / (ms * steps * 1e-3),
+               "unit": "cell-moment updates/s"}
+        if mode == "fused":
+            pts = 0
+            for k in range(s.nmom):
+                nx, ny, _, _ = s.moment_shape(k)
+                pts += nx * ny
+            size = {"fp64": 8, "fp32": 4, "bf16": 2}[precision]
+            gbs = 2 * size * pts / (ms * 1e-3) / 1e9
+            rec.update({"algorithmic_bytes_per_step": 2 * size * pts, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS})
+        out[mode] = rec
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +199,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=200, help="rows of the oracle's CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0: skip it)")
+    ap.add_argument("--fused-steps", type=int, default=20,
+                    help="timed steps of the parity-fused leg, P_7 on 1000^2 (0: skip it)")
     ap.add_argument("--models-steps", type=int, default=20,
                     help="timed steps of the FP_N / D_N model leg (0: skip it)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
@@ -245,6 +288,8 @@ def main():
     s.close()
     if args.models_steps > 0:
         out["models"] = models_leg(args.config, prec, args.models_steps)
+    if args.fused_steps > 0:
+        out["fused"] = fused_leg(7, 1000, prec, args.fused_steps)
     if args.batch > 0:
         out["batch"] = batch_leg(args.batch, "fp32")
     if not args.no_cpu_baseline:

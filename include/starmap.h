@@ -365,6 +365,21 @@ int starmap_add_field_term(starmap_solver* s, int32_t which, int32_t index, star
    STARMAP_EINVAL.  damping = NULL removes the damping. */
 int starmap_set_filter_damping(starmap_solver* s, const double* damping);
 
+/* Parity-fused passes for small orders (N <= STARMAP_FUSED_MAX_ORDER): each
+   pair of half-steps S^o, S^e of the fused composition (see starmap_advance)
+   runs as one pass over 32 x 8 tiles that holds every moment of the tile and a
+   two-point halo in LDS, computes the odd update on the tile and a one-point
+   ring around it, then the even update on the tile: every moment is read and
+   written once per step instead of three accesses per moment and step.  The
+   results are bitwise equal to the separate sweeps'.  The pass reads one state
+   buffer and writes a second one (one more state's worth of device memory).
+   Used for time-independent data without the D_N step; other solvers keep the
+   separate sweeps.  Must be chosen before the first device call
+   (STARMAP_ESTATE); N too high, the learned closure, or a tile that does not
+   fit the device's LDS: STARMAP_EINVAL. */
+#define STARMAP_FUSED_MAX_ORDER 7
+int starmap_set_fused(starmap_solver* s, int32_t enable);
+
 /* Diffusion-corrected P_N (D_N; Sect. 7: a diffusion step on the moments of
    the highest order fits the splitting): every step becomes
    S^o_{dt/2} S^e_{dt/2} D_dt S^e_{dt/2} S^o_{dt/2} with

@@ -22,6 +22,7 @@ CLOSURE_PARAMS = 33798
 FIELD_ABSORPTION, FIELD_SCATTERING, FIELD_SOURCE, FIELD_INITIAL = 0, 1, 2, 3
 FIELD_SCATTERING_ORDER = 4
 MAX_FIELD_TERMS = 32
+FUSED_MAX_ORDER = 7
 
 _ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EUNSTABLE: "EUNSTABLE", ESTATE: "ESTATE"}
 
@@ -69,6 +70,7 @@ SIGNATURES = [
     ("starmap_set_initial", [_vp, ctypes.c_int32, FIELD_FN, _vp], ctypes.c_int),
     ("starmap_set_filter_damping", [_vp, _dp], ctypes.c_int),
     ("starmap_set_diffusion", [_vp, FIELD_FN, _vp], ctypes.c_int),
+    ("starmap_set_fused", [_vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_add_field_term", [_vp, ctypes.c_int32, ctypes.c_int32, FIELD_FN, _vp, TIME_FN, _vp], ctypes.c_int),
     ("starmap_set_field_array", [_vp, ctypes.c_int32, ctypes.c_int32, _dp], ctypes.c_int),
     ("starmap_moment_shape", [_vp, ctypes.c_int32, _i32p, _i32p, _dp, _dp], ctypes.c_int),

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstarmap.so")
-SOURCES = ["plan.cpp", "sweep.hip", "mlp.hip", "materials.hip", "diffusion.hip", "capi.cpp", "closure.cpp"]
+SOURCES = ["plan.cpp", "sweep.hip", "mlp.hip", "materials.hip", "diffusion.hip", "fused.hip", "capi.cpp", "closure.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -273,6 +273,93 @@ void plan_separable(starmap_solver* s) {
   }
 }
 
+// Per-moment table of the parity-fused pass, 16 ints a moment: {gx, gy,
+// decay plane, source plane}, {n_x, n_y, 0, 0}, four x and four y couplings
+// (the coefficients are the separate sweeps' own: -M(k, j) / dx and
+// -M(k, j) / dy in the rows' order); then the moments with odd parity, then
+// those with even parity.
+void plan_fused(starmap_solver* s) {
+  s->ftab.assign(size_t(s->nmom) * 16, 0);
+  s->fcoef.assign(size_t(s->nmom) * 8, 0.0);
+  std::vector<int32_t> odd, even;
+  for (int k = 0; k < s->nmom; ++k) {
+    const auto& mk = s->moms[k];
+    int32_t* t = &s->ftab[size_t(k) * 16];
+    double* cf = &s->fcoef[size_t(k) * 8];
+    const CouplingRow& r = s->rows[k];
+    t[0] = mk.gx;
+    t[1] = mk.gy;
+    t[2] = s->dmap.dk[k];
+    t[3] = s->qk[k];
+    t[4] = r.nx;
+    t[5] = r.ny;
+    // couplings: 2 j + o, o = 1 when moment j is cell centred along the axis
+    for (int i = 0; i < r.nx; ++i) {
+      const int j = r.x[i].col;
+      t[8 + i] = 2 * j + (s->moms[j].gx == 1 ? 1 : 0);
+      cf[i] = -r.x[i].val / s->dx;
+    }
+    for (int i = 0; i < r.ny; ++i) {
+      const int j = r.y[i].col;
+      t[12 + i] = 2 * j + (s->moms[j].gy == 1 ? 1 : 0);
+      cf[4 + i] = -r.y[i].val / s->dy;
+    }
+    (mk.gx == mk.gy ? even : odd).push_back(k);
+  }
+  s->fnodd = int(odd.size());
+  s->ftab.insert(s->ftab.end(), odd.begin(), odd.end());
+  s->ftab.insert(s->ftab.end(), even.begin(), even.end());
+  s->fused_ready = false;
+}
+
+int upload_fused(starmap_solver* s) {
+  HIP_TRY(hipMemcpyAsync(dptr(s, s->off_ftab), s->ftab.data(), s->ftab.size() * 4, hipMemcpyHostToDevice,
+                         s->stream));
+  if (s->csize == 8) {
+    HIP_TRY(hipMemcpyAsync(dptr(s, s->off_ftab + align256(s->ftab.size() * 4)), s->fcoef.data(),
+                           s->fcoef.size() * 8, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else {
+    std::vector<float> cf(s->fcoef.begin(), s->fcoef.end());
+    HIP_TRY(hipMemcpyAsync(dptr(s, s->off_ftab + align256(s->ftab.size() * 4)), cf.data(), cf.size() * 4,
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  s->fused_ready = true;
+  return STARMAP_OK;
+}
+
+// One parity-fused pass: S^o_tau_odd then S^e_tau_even, state read from the
+// buffer at off_in and written to the one at off_out.
+int fused_pass(starmap_solver* s, size_t off_in, size_t off_out, double tau_odd, double tau_even) {
+  if (!s->fused_ready) {
+    int rc = upload_fused(s);
+    if (rc) return rc;
+  }
+  FusedArgs f;
+  f.uin = dptr(s, off_in);
+  f.uout = dptr(s, off_out);
+  f.src = dptr(s, s->off_src);
+  f.decay = dptr(s, s->off_decay);
+  f.tab = reinterpret_cast<const int*>(dptr(s, s->off_ftab));
+  f.coef = dptr(s, s->off_ftab + align256(size_t(s->nmom) * 16 * 4 + size_t(s->nmom) * 4));
+  f.order = f.tab + 16 * s->nmom;
+  f.ps = uint32_t(s->plane_stride);
+  f.pitch = s->pitch;
+  f.nx = s->nx;
+  f.ny = s->ny;
+  f.px = s->px;
+  f.py = s->py;
+  f.ntx = (s->nx + 1 + 31) / 32;
+  f.nty = (s->ny + 1 + 7) / 8;
+  f.nmom = s->nmom;
+  f.nodd = s->fnodd;
+  f.tau_odd = tau_odd;
+  f.tau_even = tau_even;
+  HIP_TRY(launch_fused(s->storage, f, s->stream));
+  return STARMAP_OK;
+}
+
 void layout(starmap_solver* s) {
   // decay planes and source planes
   s->dmap = decay_map(s->N, s->anisotropic);
@@ -339,6 +426,13 @@ void layout(starmap_solver* s) {
     off += nd * s->plane_bytes_c();
     s->off_dtab = off;
     off += align256(nd * 3 * 4);
+  }
+  if (s->fused) {
+    plan_fused(s);
+    s->off_state2 = off;
+    off += size_t(s->nmom) * s->plane_bytes_state();
+    s->off_ftab = off;
+    off += align256(s->ftab.size() * 4) + align256(s->fcoef.size() * s->csize);
   }
   s->dev_bytes = off;
 }
@@ -984,6 +1078,19 @@ int starmap_set_filter_damping(starmap_solver* s, const double* damping) {
   return STARMAP_OK;
 }
 
+int starmap_set_fused(starmap_solver* s, int32_t enable) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (s->device_ready) return fail(STARMAP_ESTATE, "the fused mode must be chosen before the first device call");
+  if (enable && s->N > STARMAP_FUSED_MAX_ORDER)
+    return fail(STARMAP_EINVAL, "parity-fused passes hold all moments of a tile in LDS: order too high");
+  if (enable && s->closure) return fail(STARMAP_EINVAL, "parity-fused passes do not take the learned closure");
+  if (enable && fused_lds_bytes(s->storage, s->nmom) > size_t(max_lds_bytes()))
+    return fail(STARMAP_EINVAL, "parity-fused tile does not fit the LDS");
+  s->fused = enable != 0;
+  layout(s);
+  return STARMAP_OK;
+}
+
 int starmap_set_diffusion(starmap_solver* s, starmap_field_fn kappa, void* ctx) {
   if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
   if (s->device_ready) return fail(STARMAP_ESTATE, "the D_N diffusion must be set before the first device call");
@@ -1103,7 +1210,25 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
     if (!r) r = sweep(s, 0, 0.5 * dt);
     return r;
   };
-  if (!s->time_dependent && !s->separable) {
+  if (!s->time_dependent && !s->separable && s->fused && !s->has_diffusion) {
+    // pairs (S^o, S^e) in one pass each, ping-ponging between two state
+    // buffers, then the closing odd half-step
+    if (!s->materials_ready) {
+      rc = upload_materials(s, s->t + 0.5 * dt);
+      if (rc) return rc;
+    }
+    size_t cur = s->off_state, other = s->off_state2;
+    for (int64_t i = 0; i < nsteps; ++i) {
+      rc = fused_pass(s, cur, other, i == 0 ? 0.5 * dt : dt, dt);
+      if (rc) return rc;
+      std::swap(cur, other);
+    }
+    if (cur != s->off_state)
+      HIP_TRY(hipMemcpyAsync(dptr(s, s->off_state), dptr(s, cur), size_t(s->nmom) * s->plane_bytes_state(),
+                             hipMemcpyDeviceToDevice, s->stream));
+    rc = sweep(s, 1, 0.5 * dt);
+    if (rc) return rc;
+  } else if (!s->time_dependent && !s->separable) {
     if (!s->materials_ready) {
       rc = upload_materials(s, s->t + 0.5 * dt);
       if (rc) return rc;

@@ -40,6 +40,20 @@ __device__ __forceinline__ C expm1div(C z) {
   return z == C(0) ? C(1) : expm1_c(z) / z;
 }
 
+// The two pieces of arithmetic of an update, with their fused multiply-adds
+// spelled out so that every kernel that applies them (the separate sweeps,
+// the batched sweep, the parity-fused pass) rounds identically:
+// one coupling term of the residual, W + cf (hi - lo), and the exact sub-step
+// u + tau (W - c u) E.
+template <typename C>
+__device__ __forceinline__ C couple(C W, C cf, C hi, C lo) {
+  return fma(cf, hi - lo, W);
+}
+template <typename C>
+__device__ __forceinline__ C sub_step(C u, C W, C c, C E, C tau) {
+  return fma(tau * fma(-c, u, W), E, u);
+}
+
 // Index of an LDS staging load along one axis: periodic grids wrap, the others
 // clamp to the last stored point (the constant-extrapolation ghosts of cell
 // grids are exactly the clamped neighbours; clamped nodal points beyond the
@@ -61,6 +75,34 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   // XCD x owns tiles [start(x), start(x) + q + (x < r))
   const int start = xcd * q + (xcd < r ? xcd : r);
   return start + idx;
+}
+
+// Kernel tables (sweep programs, coupling records) are read-only during a
+// launch and read at wave-uniform addresses: held as
+// constant-address-space pointers, those reads are scalar loads wherever the
+// pointer comes from (a kernel argument or an instance table in memory).
+template <typename P>
+using cptr = __attribute__((address_space(4))) const P*;
+
+// Plane k of an array of planes of ps elements: a 32 x 32 -> 64-bit product
+// (plane strides and plane counts fit 32 bits), cheaper in scalar
+// instructions than a 64-bit multiply.
+template <typename P>
+__device__ __forceinline__ P* plane_at(P* base, int k, uint32_t ps) {
+  return base + uint64_t(uint32_t(k)) * uint64_t(ps);
+}
+
+// Table entry at a 32-bit byte offset (non-negative indices): the scalar load
+// takes the offset as its own operand, with no 64-bit address arithmetic.
+template <typename P>
+__device__ __forceinline__ cptr<P> cat(cptr<P> t, uint32_t byte_off) {
+  return reinterpret_cast<cptr<P>>(reinterpret_cast<cptr<char>>(t) + byte_off);
+}
+
+// Entry i of a table of int4 records.
+__device__ __forceinline__ int4 rec4(cptr<int> t, int i) {
+  const cptr<int> q = cat(t, uint32_t(i) * 16u);
+  return make_int4(q[0], q[1], q[2], q[3]);
 }
 
 }  // namespace starmap

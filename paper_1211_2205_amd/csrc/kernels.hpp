@@ -106,6 +106,35 @@ struct DiffusionArgs {
 };
 hipError_t launch_diffusion(int storage, const DiffusionArgs& a, int max_points, hipStream_t stream);
 
+// Parity-fused pass (small orders): S^o_tau_odd then S^e_tau_even on tiles of
+// 32 x 8 points, all moments of a tile in LDS.  Reads uin (state planes),
+// writes uout (another buffer of state planes); sources at src (plane
+// tab[16k+3] of src, or none), decay planes at decay.  tab holds 16 ints per
+// moment: grid classes gx, gy (1 = cell, 2 = node), decay plane, source plane
+// or -1, number of x and y couplings, the coupled moments (4 + 4), unused;
+// coef holds the 8 coupling coefficients of the separate sweeps' programs;
+// order lists the odd moments (nodd of them), then the even ones.
+template <typename C>
+struct FusedScalars {
+  uint32_t ps;
+  int pitch, nx, ny, px, py, ntx, nty, nmom, nodd;
+  C tau_odd, tau_even;
+};
+struct FusedArgs {
+  const void* uin;
+  void* uout;
+  const void* src;
+  const void* decay;
+  const int* tab;
+  const void* coef;
+  const int* order;
+  uint32_t ps;
+  int pitch, nx, ny, px, py, ntx, nty, nmom, nodd;
+  double tau_odd, tau_even;
+};
+size_t fused_lds_bytes(int storage, int nmom);
+hipError_t launch_fused(int storage, const FusedArgs& f, hipStream_t stream);
+
 // FP64 diagnostics of a state: mass of plane 0 (times cell area is applied on
 // the host), sum of squares and max |u| over all valid points, count of
 // non-finite values.  part must hold 4 * nblocks doubles, out 4 doubles.

@@ -81,6 +81,12 @@ struct starmap_solver {
   // diffusion-corrected P_N: kappa of the diffusion step on the order-N moments
   starmap::detail::FieldSource diffusion;
   bool has_diffusion = false;
+  // parity-fused passes (small orders): second state buffer and the per-moment table
+  bool fused = false, fused_ready = false;
+  size_t off_state2 = 0, off_ftab = 0;
+  std::vector<int32_t> ftab;   // 16 ints per moment, then the moment order (odd first)
+  std::vector<double> fcoef;   // 8 coefficients per moment
+  int fnodd = 0;
   size_t off_dtmp = 0, off_kappa = 0, off_dtab = 0;  // scratch planes, kappa planes, plane table
   bool diffusion_ready = false;
   bool time_dependent = false;
@@ -161,6 +167,8 @@ int ensure_device(starmap_solver* s);
 int upload_materials(starmap_solver* s, double t_eval);
 // Materials of a time-independent or separable problem at t_eval.
 int ensure_materials(starmap_solver* s, double t_eval);
+// Largest dynamic LDS of one workgroup on the current device (64 KiB without one).
+int max_lds_bytes();
 
 // Closure (closure.cpp): geometry of a solver's closure inputs, and the
 // fused closure kernel run before every odd sweep of a closure solver.

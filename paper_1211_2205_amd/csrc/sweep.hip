@@ -69,34 +69,6 @@ __device__ __forceinline__ bf16 load_stream(const bf16* p) {
 // (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
 
-// The sweep programs (m ranges, orders, staging loads, rows, coefficients) are
-// read-only during a launch and read at wave-uniform addresses: held as
-// constant-address-space pointers, those reads are scalar loads wherever the
-// pointer comes from (a kernel argument or an instance table in memory).
-template <typename P>
-using cptr = __attribute__((address_space(4))) const P*;
-
-// Plane k of an array of planes of ps elements: a 32 x 32 -> 64-bit product
-// (plane strides and plane counts fit 32 bits), cheaper in scalar
-// instructions than a 64-bit multiply.
-template <typename P>
-__device__ __forceinline__ P* plane_at(P* base, int k, uint32_t ps) {
-  return base + uint64_t(uint32_t(k)) * uint64_t(ps);
-}
-
-// Table entry at a 32-bit byte offset (non-negative indices): the scalar load
-// takes the offset as its own operand, with no 64-bit address arithmetic.
-template <typename P>
-__device__ __forceinline__ cptr<P> cat(cptr<P> t, uint32_t byte_off) {
-  return reinterpret_cast<cptr<P>>(reinterpret_cast<cptr<char>>(t) + byte_off);
-}
-
-// Entry i of a table of int4 records.
-__device__ __forceinline__ int4 rec4(cptr<int> t, int i) {
-  const cptr<int> q = cat(t, uint32_t(i) * 16u);
-  return make_int4(q[0], q[1], q[2], q[3]);
-}
-
 // Body of one workgroup's work in a sweep: spatial tile and m range number lb
 // (lb = tile * nchunks + range) of one instance.
 template <typename T, int TX, int TY, int CAP>
@@ -353,12 +325,12 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
               const T* lp = L + rec[4 + t] + pos[p];
-              W += cf[t] * (to_c(lp[1]) - to_c(lp[0]));
+              W = couple(W, cf[t], to_c(lp[1]), to_c(lp[0]));
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
               const T* lp = L + rec[8 + t] + pos[p];
-              W += cf[4 + t] * (to_c(lp[LW]) - to_c(lp[0]));
+              W = couple(W, cf[4 + t], to_c(lp[LW]), to_c(lp[0]));
             }
     // the source, staged in LDS, joins the residual
             if (so >= 0) W += to_c(L[so + pos[p]]);
@@ -366,7 +338,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
               const C c = gslot ? c1[p] : c0[p];
               const C E = gslot ? e1[p] : e0[p];
               const C u = ua[i][p];
-              store_stream(at(up, goff[p] * TS), from_c<T>(u + a.tau * (W - c * u) * E));
+              store_stream(at(up, goff[p] * TS), from_c<T>(sub_step(u, W, c, E, a.tau)));
             }
           }
         }

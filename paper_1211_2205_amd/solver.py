@@ -209,6 +209,11 @@ class Solver:
             raise ValueError(f"filter damping needs N + 1 = {self.N + 1} values")
         B.check(B.lib().starmap_set_filter_damping(self._h, d.ctypes.data_as(B._dp)))
 
+    def set_fused(self, enable=True):
+        """Parity-fused passes (orders up to 7): each step's odd and even
+        half-steps in one pass over the state; bitwise equal results."""
+        B.check(B.lib().starmap_set_fused(self._h, int(bool(enable))))
+
     def set_diffusion(self, kappa):
         """Diffusion-corrected P_N: kappa(t, x, y) of the diffusion step on the
         order-N moments (sampled once); None removes it."""

@@ -201,3 +201,18 @@ def test_fpn_and_dn_settings_are_validated_on_the_host():
     c = pa.Solver(5, (12, 12), (0, 1, 0, 1), closure="learned")
     with pytest.raises(pa.StarmapError):
         c.set_diffusion(lambda t, x, y: 0.001 + 0 * x)
+
+
+def test_fused_mode_is_validated_on_the_host():
+    # FP32: the tile fits the 64 KiB assumed without a device
+    s = pa.Solver(5, (40, 30), (0, 1, 0, 1), precision="fp32")
+    base = s.workspace_bytes()
+    s.set_fused(True)
+    # a second state buffer and the per-moment table
+    assert s.workspace_bytes() > base + pa.num_moments(5) * 41 * 31 * 4
+    s.set_fused(False)
+    assert s.workspace_bytes() == base
+    with pytest.raises(pa.StarmapError):
+        pa.Solver(pa._binding.FUSED_MAX_ORDER + 1, (20, 20), (0, 1, 0, 1)).set_fused(True)
+    with pytest.raises(pa.StarmapError):
+        pa.Solver(5, (20, 20), (0, 1, 0, 1), closure="learned").set_fused(True)
