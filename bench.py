@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0: skip it)")
     ap.add_argument("--fused-steps", type=int, default=20,
-                    help="timed steps of the parity-fused leg, P_7 on 1000^2 (0: skip it)")
+                    help="timed steps of the parity-fused leg, P_7 on 1000^2 and 2048^2 (0: skip it)")
     ap.add_argument("--models-steps", type=int, default=20,
                     help="timed steps of the FP_N / D_N model leg (0: skip it)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
@@ -289,7 +289,9 @@ def main():
     if args.models_steps > 0:
         out["models"] = models_leg(args.config, prec, args.models_steps)
     if args.fused_steps > 0:
-        out["fused"] = fused_leg(7, 1000, prec, args.fused_steps)
+        # 1000^2: one state copy (144 MB in FP32) stays in the 256 MB last-level
+        # cache; 2048^2 (604 MB) does not
+        out["fused"] = [fused_leg(7, n, prec, args.fused_steps) for n in (1000, 2048)]
     if args.batch > 0:
         out["batch"] = batch_leg(args.batch, "fp32")
     if not args.no_cpu_baseline:

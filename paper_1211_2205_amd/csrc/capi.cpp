@@ -273,42 +273,51 @@ void plan_separable(starmap_solver* s) {
   }
 }
 
-// Per-moment table of the parity-fused pass, 16 ints a moment: {gx, gy,
-// decay plane, source plane}, {n_x, n_y, 0, 0}, four x and four y couplings
-// (the coefficients are the separate sweeps' own: -M(k, j) / dx and
-// -M(k, j) / dy in the rows' order); then the moments with odd parity, then
-// those with even parity.
+// Table of the parity-fused pass, one 16-int record per moment in processing
+// order (the moments with odd parity, then those with even parity):
+// {gx, gy, decay plane, source plane}, {k, reload, 0, 0}, four x and four y
+// couplings, each 2 j + o with o = 1 when moment j is cell centred along the
+// axis.  reload = 1 when the decay plane differs from the one the previous
+// moment of the same parity and x grid class used.  Coupling lists are padded
+// to four entries with coefficient 0 on a column of the other parity.  Eight
+// coefficients per record, the separate sweeps' own (-M(k, j) / dx and
+// -M(k, j) / dy in the rows' order).
 void plan_fused(starmap_solver* s) {
+  std::vector<int32_t> odd, even;
+  for (int k = 0; k < s->nmom; ++k) (s->moms[k].gx == s->moms[k].gy ? even : odd).push_back(k);
+  std::vector<int32_t> order = odd;
+  order.insert(order.end(), even.begin(), even.end());
   s->ftab.assign(size_t(s->nmom) * 16, 0);
   s->fcoef.assign(size_t(s->nmom) * 8, 0.0);
-  std::vector<int32_t> odd, even;
-  for (int k = 0; k < s->nmom; ++k) {
+  int last_dk[2][2] = {{-1, -1}, {-1, -1}};  // [parity][x grid class]
+  for (int q = 0; q < s->nmom; ++q) {
+    const int k = order[q];
     const auto& mk = s->moms[k];
-    int32_t* t = &s->ftab[size_t(k) * 16];
-    double* cf = &s->fcoef[size_t(k) * 8];
+    const int parity = mk.gx == mk.gy ? 1 : 0;
+    int32_t* t = &s->ftab[size_t(q) * 16];
+    double* cf = &s->fcoef[size_t(q) * 8];
     const CouplingRow& r = s->rows[k];
     t[0] = mk.gx;
     t[1] = mk.gy;
     t[2] = s->dmap.dk[k];
     t[3] = s->qk[k];
-    t[4] = r.nx;
-    t[5] = r.ny;
-    // couplings: 2 j + o, o = 1 when moment j is cell centred along the axis
-    for (int i = 0; i < r.nx; ++i) {
-      const int j = r.x[i].col;
-      t[8 + i] = 2 * j + (s->moms[j].gx == 1 ? 1 : 0);
-      cf[i] = -r.x[i].val / s->dx;
+    t[4] = k;
+    int& last = last_dk[parity][mk.gx == 1 ? 1 : 0];
+    t[5] = t[2] != last ? 1 : 0;
+    last = t[2];
+    const std::vector<int32_t>& others = parity ? odd : even;
+    const int other = others.empty() ? k : others[0];  // P_0 has no couplings
+    for (int i = 0; i < 4; ++i) {
+      const int jx = i < r.nx ? r.x[i].col : (r.nx ? r.x[0].col : other);
+      const int jy = i < r.ny ? r.y[i].col : (r.ny ? r.y[0].col : other);
+      t[8 + i] = 2 * jx + (s->moms[jx].gx == 1 ? 1 : 0);
+      t[12 + i] = 2 * jy + (s->moms[jy].gy == 1 ? 1 : 0);
+      cf[i] = i < r.nx ? -r.x[i].val / s->dx : 0.0;
+      cf[4 + i] = i < r.ny ? -r.y[i].val / s->dy : 0.0;
     }
-    for (int i = 0; i < r.ny; ++i) {
-      const int j = r.y[i].col;
-      t[12 + i] = 2 * j + (s->moms[j].gy == 1 ? 1 : 0);
-      cf[4 + i] = -r.y[i].val / s->dy;
-    }
-    (mk.gx == mk.gy ? even : odd).push_back(k);
   }
+  for (int d = 0; d < s->dmap.nplanes; ++d) s->ftab.insert(s->ftab.end(), {s->dmap.plane_gx[d], s->dmap.plane_gy[d], 0, 0});
   s->fnodd = int(odd.size());
-  s->ftab.insert(s->ftab.end(), odd.begin(), odd.end());
-  s->ftab.insert(s->ftab.end(), even.begin(), even.end());
   s->fused_ready = false;
 }
 
@@ -342,8 +351,7 @@ int fused_pass(starmap_solver* s, size_t off_in, size_t off_out, double tau_odd,
   f.src = dptr(s, s->off_src);
   f.decay = dptr(s, s->off_decay);
   f.tab = reinterpret_cast<const int*>(dptr(s, s->off_ftab));
-  f.coef = dptr(s, s->off_ftab + align256(size_t(s->nmom) * 16 * 4 + size_t(s->nmom) * 4));
-  f.order = f.tab + 16 * s->nmom;
+  f.coef = dptr(s, s->off_ftab + align256(s->ftab.size() * 4));
   f.ps = uint32_t(s->plane_stride);
   f.pitch = s->pitch;
   f.nx = s->nx;
@@ -354,6 +362,7 @@ int fused_pass(starmap_solver* s, size_t off_in, size_t off_out, double tau_odd,
   f.nty = (s->ny + 1 + 7) / 8;
   f.nmom = s->nmom;
   f.nodd = s->fnodd;
+  f.nd = s->dmap.nplanes;
   f.tau_odd = tau_odd;
   f.tau_even = tau_even;
   HIP_TRY(launch_fused(s->storage, f, s->stream));
@@ -704,6 +713,10 @@ int upload_initial(starmap_solver* s) {
 
 int ensure_device(starmap_solver* s) {
   if (s->device_ready) return STARMAP_OK;
+  // decay planes may have been added (anisotropic scattering, filter damping)
+  // after the fused mode was chosen
+  if (s->fused && fused_lds_bytes(s->storage, s->nmom, s->dmap.nplanes) > size_t(max_lds_bytes()))
+    return fail(STARMAP_EINVAL, "parity-fused tile (moments and decay planes) does not fit the LDS");
   int rc = ensure_stream(s);
   if (rc) return rc;
   if (!s->dev) {
@@ -1084,8 +1097,8 @@ int starmap_set_fused(starmap_solver* s, int32_t enable) {
   if (enable && s->N > STARMAP_FUSED_MAX_ORDER)
     return fail(STARMAP_EINVAL, "parity-fused passes hold all moments of a tile in LDS: order too high");
   if (enable && s->closure) return fail(STARMAP_EINVAL, "parity-fused passes do not take the learned closure");
-  if (enable && fused_lds_bytes(s->storage, s->nmom) > size_t(max_lds_bytes()))
-    return fail(STARMAP_EINVAL, "parity-fused tile does not fit the LDS");
+  if (enable && fused_lds_bytes(s->storage, s->nmom, s->dmap.nplanes) > size_t(max_lds_bytes()))
+    return fail(STARMAP_EINVAL, "parity-fused tile (moments and decay planes) does not fit the LDS");
   s->fused = enable != 0;
   layout(s);
   return STARMAP_OK;

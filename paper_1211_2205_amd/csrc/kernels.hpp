@@ -117,7 +117,7 @@ hipError_t launch_diffusion(int storage, const DiffusionArgs& a, int max_points,
 template <typename C>
 struct FusedScalars {
   uint32_t ps;
-  int pitch, nx, ny, px, py, ntx, nty, nmom, nodd;
+  int pitch, nx, ny, px, py, ntx, nty, nmom, nodd, nd;
   C tau_odd, tau_even;
 };
 struct FusedArgs {
@@ -127,12 +127,11 @@ struct FusedArgs {
   const void* decay;
   const int* tab;
   const void* coef;
-  const int* order;
   uint32_t ps;
-  int pitch, nx, ny, px, py, ntx, nty, nmom, nodd;
+  int pitch, nx, ny, px, py, ntx, nty, nmom, nodd, nd;
   double tau_odd, tau_even;
 };
-size_t fused_lds_bytes(int storage, int nmom);
+size_t fused_lds_bytes(int storage, int nmom, int nd);
 hipError_t launch_fused(int storage, const FusedArgs& f, hipStream_t stream);
 
 // FP64 diagnostics of a state: mass of plane 0 (times cell area is applied on
