@@ -53,24 +53,34 @@ def _traffic(launch_bytes, precision):
 
 def cpu_baseline(prob, rows):
     """Oracle (FP64, plain C + OpenMP) on a band of `rows` grid rows of the same
-    workload for one full step."""
+    workload for one full step, on all host threads; then on one thread over a
+    band a tenth as high."""
     import workloads as wl
+    from oracle import scheme
     from oracle.scheme import OracleSolver
     h = (prob.ax[1] - prob.ax[0]) / prob.n[0]
-    band = wl.line_source(N=prob.N, n=prob.n[0], s=0.01, precision="fp64")
-    band.n = (prob.n[0], rows)
-    band.ax = (prob.ax[0], prob.ax[1], -rows * h / 2, rows * h / 2)
-    o = OracleSolver(band)
-    o.evaluate_materials(0.0)
-    t0 = time.perf_counter()
-    o.step()
-    t1 = time.perf_counter()
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    updates = prob.n[0] * rows * o.nmom
-    return {"value": updates / (t1 - t0), "unit": "cell-moment updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"one full step (4 half-steps) of P_{prob.N} on a {prob.n[0]} x {rows} band "
-                      f"({updates:.3e} cell-moment updates, {t1 - t0:.1f} s, FP64)"}
+
+    def run(r):
+        band = wl.line_source(N=prob.N, n=prob.n[0], s=0.01, precision="fp64")
+        band.n = (prob.n[0], r)
+        band.ax = (prob.ax[0], prob.ax[1], -r * h / 2, r * h / 2)
+        o = OracleSolver(band)
+        o.evaluate_materials(0.0)
+        t0 = time.perf_counter()
+        o.step()
+        t1 = time.perf_counter()
+        updates = prob.n[0] * r * o.nmom
+        return updates / (t1 - t0), (f"one full step (4 half-steps) of P_{prob.N} on a {prob.n[0]} x {r} band "
+                                     f"({updates:.3e} cell-moment updates, {t1 - t0:.1f} s, FP64)")
+
+    all_threads = scheme.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0)))
+    v, sample = run(rows)
+    scheme.set_threads(1)
+    v1, sample1 = run(max(rows // 10, 4))
+    scheme.set_threads(all_threads)
+    return {"value": v, "unit": "cell-moment updates/s", "cores": all_threads, "kind": "oracle",
+            "sample": sample,
+            "single_thread": {"value": v1, "unit": "cell-moment updates/s", "cores": 1, "sample": sample1}}
 
 
 def batch_leg(count, precision):

@@ -66,8 +66,21 @@ def lib():
                                                                 ctypes.c_double, ctypes.c_int]
         L.starmap_oracle_expm1div.argtypes = [ctypes.c_double, ctypes.c_int]
         L.starmap_oracle_expm1div.restype = ctypes.c_double
+        L.starmap_oracle_set_threads.argtypes = [ctypes.c_int]
+        L.starmap_oracle_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's row loops (timing only; results do not
+    depend on it).  Returns the count now in effect."""
+    lib().starmap_oracle_set_threads(int(n))
+    return lib().starmap_oracle_threads()
+
+
+def threads() -> int:
+    return lib().starmap_oracle_threads()
 
 
 def expm1div(z: float, mode: int = 0) -> float:

@@ -19,6 +19,7 @@
  * for any thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -42,6 +43,12 @@ static double expm1div(double z, int mode) {
 }
 
 double starmap_oracle_expm1div(double z, int mode) { return expm1div(z, mode); }
+
+/* Thread count of the row loops (timing only: results do not depend on it). */
+void starmap_oracle_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+int starmap_oracle_threads(void) { return omp_get_max_threads(); }
 
 /*
  * D_x of a field on grid (tx, ty) -> field on grid (3 - tx, ty).
