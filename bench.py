@@ -211,6 +211,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0: skip it)")
     ap.add_argument("--fused-steps", type=int, default=20,
                     help="timed steps of the parity-fused leg, P_7 on 1000^2 and 2048^2 (0: skip it)")
+    ap.add_argument("--fused-orders", default="7", help="orders of the parity-fused leg (comma-separated)")
+    ap.add_argument("--fused-cells", default="1000,2048", help="grid sizes n (n x n) of the parity-fused leg")
     ap.add_argument("--models-steps", type=int, default=20,
                     help="timed steps of the FP_N / D_N model leg (0: skip it)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
@@ -292,7 +294,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": "sweep_kernel", "avg_launch_ms": kernel_ms / launches,
-                     "algorithmic_bytes_per_launch": per_launch},
+                     "algorithmic_bytes_per_launch": per_launch,
+                     # HBM bytes of the counter runs over this run's launch time, and
+                     # the design's 3 s bytes per cell-moment update at the measured rate
+                     "hbm_GBs": traffic / (kernel_ms / launches * 1e-3) / 1e9 if traffic else None,
+                     "effective_GBs": 3 * {"fp64": 8, "fp32": 4, "bf16": 2}[prec] * updates / wall / 1e9},
         "state_check": {"mass": diag["mass"], "l2": diag["l2"], "nonfinite": diag["nonfinite"]},
     }
     s.close()
@@ -301,7 +307,8 @@ def main():
     if args.fused_steps > 0:
         # 1000^2: one state copy (144 MB in FP32) stays in the 256 MB last-level
         # cache; 2048^2 (604 MB) does not
-        out["fused"] = [fused_leg(7, n, prec, args.fused_steps) for n in (1000, 2048)]
+        out["fused"] = [fused_leg(int(N), int(n), prec, args.fused_steps)
+                        for N in args.fused_orders.split(",") for n in args.fused_cells.split(",")]
     if args.batch > 0:
         out["batch"] = batch_leg(args.batch, "fp32")
     if not args.no_cpu_baseline:
