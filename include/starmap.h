@@ -367,16 +367,22 @@ int starmap_set_filter_damping(starmap_solver* s, const double* damping);
 
 /* Parity-fused passes for small orders (N <= STARMAP_FUSED_MAX_ORDER): each
    pair of half-steps S^o, S^e of the fused composition (see starmap_advance)
-   runs as one pass over 32 x 8 tiles that holds every moment of the tile and a
-   two-point halo in LDS, computes the odd update on the tile and a one-point
-   ring around it, then the even update on the tile: every moment is read and
-   written once per step instead of three accesses per moment and step.  The
-   results are bitwise equal to the separate sweeps'.  The pass reads one state
+   runs as one pass over 32 x 8 tiles that holds every moment and every decay
+   plane of the tile and a two-point halo in LDS, computes the odd update on
+   the tile and a one-point ring around it, then the even update on the tile:
+   every moment is read and written once per step instead of three accesses
+   per moment and step (Sect. 4.3 applies the two sub-steps in turn; fusing
+   them over a tile is this library's schedule).  The results are bitwise
+   equal to the separate sweeps' for finite states.  The pass reads one state
    buffer and writes a second one (one more state's worth of device memory).
    Used for time-independent data without the D_N step; other solvers keep the
-   separate sweeps.  Must be chosen before the first device call
+   separate sweeps.  An option, not a speed-up on every device: on MI355X the
+   LDS footprint limits a compute unit to two such tiles and the separate
+   sweeps are faster.  Must be chosen before the first device call
    (STARMAP_ESTATE); N too high, the learned closure, or a tile that does not
-   fit the device's LDS: STARMAP_EINVAL. */
+   fit the device's LDS: STARMAP_EINVAL (a tile that stops fitting because
+   per-order decay planes were added later fails the first device call with
+   STARMAP_EINVAL). */
 #define STARMAP_FUSED_MAX_ORDER 7
 int starmap_set_fused(starmap_solver* s, int32_t enable);
 
