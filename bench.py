@@ -53,8 +53,8 @@ def _traffic(launch_bytes, precision):
 
 def cpu_baseline(prob, rows):
     """Oracle (FP64, plain C + OpenMP) on a band of `rows` grid rows of the same
-    workload for one full step, on all host threads; then on one thread over a
-    band a tenth as high."""
+    workload for one full step, on all host threads, then on one thread (the
+    same band: the oracle is memory-bound, a smaller band would sit in cache)."""
     import workloads as wl
     from oracle import scheme
     from oracle.scheme import OracleSolver
@@ -76,7 +76,7 @@ def cpu_baseline(prob, rows):
     all_threads = scheme.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0)))
     v, sample = run(rows)
     scheme.set_threads(1)
-    v1, sample1 = run(max(rows // 10, 4))
+    v1, sample1 = run(rows)
     scheme.set_threads(all_threads)
     return {"value": v, "unit": "cell-moment updates/s", "cores": all_threads, "kind": "oracle",
             "sample": sample,

@@ -85,3 +85,24 @@ def test_fused_errors_and_fallbacks():
     a = _run(prob, False)
     b = _run(prob, True)
     assert _identical(a, b)
+
+
+def test_fused_lds_check_with_per_order_decay_planes():
+    """FP64 P_7 with per-order decay planes (FP_N) needs 36 moment planes and
+    16 decay planes of a 36 x 12 tile, 175.5 KB, more than a compute unit's
+    LDS: refused whichever of the two calls comes first, before any launch."""
+    _say("fused: FP64 P_7 FP_N LDS check")
+    prob = wl.line_source(N=7, n=40, s=0.1, half_width=1.0, t_final=0.1, precision="fp64")
+    damping = [0.0] + [0.1 * l for l in range(1, 8)]
+    s = pa.Solver.from_problem(prob)
+    s.set_fused(True)  # isotropic: 36 + 5 planes, 138 KB, fits
+    s.set_filter_damping(damping)
+    with pytest.raises(pa.StarmapError):
+        s.advance(1)
+    s.close()
+    s = pa.Solver.from_problem(prob)
+    s.set_filter_damping(damping)
+    with pytest.raises(pa.StarmapError):
+        s.set_fused(True)
+    s.advance(1)  # still usable with the separate sweeps
+    s.close()
