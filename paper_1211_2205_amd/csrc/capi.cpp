@@ -275,9 +275,9 @@ void plan_separable(starmap_solver* s) {
 
 // Table of the parity-fused pass, one 16-int record per moment in processing
 // order (the moments with odd parity, then those with even parity):
-// {gx, gy, decay plane, source plane}, {k, reload, 0, 0}, four x and four y
-// couplings, each 2 j + o with o = 1 when moment j is cell centred along the
-// axis.  reload = 1 when the decay plane differs from the one the previous
+// {gx, gy, decay plane, source plane}, {k, reload, k P, 0}, four x and four y
+// couplings as LDS offsets j P - o and j P - o R (P, R: the pass's staged
+// plane and row; o = 1 when moment j is cell centred along the axis).  reload = 1 when the decay plane differs from the one the previous
 // moment of the same parity and x grid class used.  Coupling lists are padded
 // to four entries with coefficient 0 on a column of the other parity.  Eight
 // coefficients per record, the separate sweeps' own (-M(k, j) / dx and
@@ -302,6 +302,7 @@ void plan_fused(starmap_solver* s) {
     t[2] = s->dmap.dk[k];
     t[3] = s->qk[k];
     t[4] = k;
+    t[6] = k * kFusedPlane;
     int& last = last_dk[parity][mk.gx == 1 ? 1 : 0];
     t[5] = t[2] != last ? 1 : 0;
     last = t[2];
@@ -310,8 +311,8 @@ void plan_fused(starmap_solver* s) {
     for (int i = 0; i < 4; ++i) {
       const int jx = i < r.nx ? r.x[i].col : (r.nx ? r.x[0].col : other);
       const int jy = i < r.ny ? r.y[i].col : (r.ny ? r.y[0].col : other);
-      t[8 + i] = 2 * jx + (s->moms[jx].gx == 1 ? 1 : 0);
-      t[12 + i] = 2 * jy + (s->moms[jy].gy == 1 ? 1 : 0);
+      t[8 + i] = jx * kFusedPlane - (s->moms[jx].gx == 1 ? 1 : 0);
+      t[12 + i] = jy * kFusedPlane - (s->moms[jy].gy == 1 ? kFusedRow : 0);
       cf[i] = i < r.nx ? -r.x[i].val / s->dx : 0.0;
       cf[4 + i] = i < r.ny ? -r.y[i].val / s->dy : 0.0;
     }
@@ -358,8 +359,8 @@ int fused_pass(starmap_solver* s, size_t off_in, size_t off_out, double tau_odd,
   f.ny = s->ny;
   f.px = s->px;
   f.py = s->py;
-  f.ntx = (s->nx + 1 + 31) / 32;
-  f.nty = (s->ny + 1 + 7) / 8;
+  f.ntx = (s->nx + 1 + kFusedTX - 1) / kFusedTX;
+  f.nty = (s->ny + 1 + kFusedTY - 1) / kFusedTY;
   f.nmom = s->nmom;
   f.nodd = s->fnodd;
   f.nd = s->dmap.nplanes;

@@ -23,13 +23,16 @@ namespace {
 constexpr int kThreads = 256;
 
 // Record of one moment, four int4, in processing order (odd parity first):
-//   {gx, gy, decay plane, source plane or -1}, {k, reload, 0, 0},
-//   x couplings {2 j + o}, y couplings {2 j + o}
-// where k is the moment, reload = 1 when its decay plane differs from the one
-// last used on its grid within its parity, j a coupled moment and o = 1 when
-// moment j is cell centred along the derivative's axis (its backward
-// neighbour is one point lower).  Coupling lists are padded to four entries
-// with zero coefficients (a zero term leaves the finite sum unchanged).
+//   {gx, gy, decay plane, source plane or -1}, {k, reload, k P, 0},
+//   x couplings {j P - o}, y couplings {j P - o R}
+// where k is the moment, P the staged plane and R the staged row
+// (kFusedPlane, kFusedRow), reload = 1 when the decay plane differs from the
+// one last used on its grid within its parity, j a coupled moment and o = 1
+// when moment j is cell centred along the derivative's axis (its backward
+// neighbour is one point lower): a coupling's LDS pair is (q + 1, q) along x
+// and (q + R, q) along y with q = offset + position.  Coupling lists are
+// padded to four entries with zero coefficients (a zero term leaves the
+// finite sum unchanged).
 // Records sit at fixed offsets, so no table read waits on another.  After the
 // nmom moment records come nd int4 {gx, gy, 0, 0}: the grid of each decay
 // plane.
@@ -93,6 +96,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
   constexpr int BD = 8;                                  // decay planes staged per batch
   constexpr int G = 4;                                   // moments updated together
   static_assert(TX * TY == kThreads, "one tile point per thread");
+  static_assert(PL == kFusedPlane && W2 == kFusedRow, "the host's coupling offsets use the same staged plane");
   static_assert(RN <= 2 * kThreads, "tile and ring within two points per thread");
   extern __shared__ __align__(16) unsigned char smem[];
   T* L = reinterpret_cast<T*>(smem);                                   // nmom planes of PL
@@ -167,12 +171,12 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
     C W = C(0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int e = pick(r.jx, i), q = (e >> 1) * PL + p - (e & 1);
+      const int q = pick(r.jx, i) + p;
       W = couple(W, cf[i], to_c(L[q + 1]), to_c(L[q]));
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int e = pick(r.jy, i), q = (e >> 1) * PL + p - (e & 1) * W2;
+      const int q = pick(r.jy, i) + p;
       W = couple(W, cf[4 + i], to_c(L[q + W2]), to_c(L[q]));
     }
     return W;
@@ -194,7 +198,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
       W[g] = flux(r[g], cat(coef, uint32_t(q) * uint32_t(8 * sizeof(C))), p);
     }
 #pragma unroll
-    for (int g = 0; g < G; ++g) u[g] = to_c(L[r[g].n.x * PL + p]);
+    for (int g = 0; g < G; ++g) u[g] = to_c(L[r[g].n.z + p]);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const uint32_t off = co.of(r[g].g.x, r[g].g.y);
@@ -208,7 +212,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
     }
     if (write) {
 #pragma unroll
-      for (int g = 0; g < G; ++g) L[r[g].n.x * PL + p] = from_c<T>(u[g]);
+      for (int g = 0; g < G; ++g) L[r[g].n.z + p] = from_c<T>(u[g]);
     }
   };
 
@@ -229,16 +233,37 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
   }
   __syncthreads();
   // 3. ring positions outside the grid on an extrapolation axis take the
-  //    value of the grid point they repeat
+  //    value of the grid point they repeat; the odd moments sit on two grid
+  //    classes (cell centred along x or along y), so each ring position has
+  //    one source per class, found once
   if (!a.px || !a.py) {
+    int dst[2], src_x[2], src_y[2];  // per ring slot; source -1: no fix-up
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int e = tid + t * kThreads;
+      const int lx = e % RW - 1, ly = e / RW - 1;
+      dst[t] = (ly + 2) * W2 + lx + 2;
+      src_x[t] = src_y[t] = -1;
+      if (e < RN) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {  // c = 0: cell centred along x (nodal y); 1: along y
+          const int mx = a.px ? lx : map_axis(x0 + lx, a.nx, 0, c == 0) - x0;
+          const int my = a.py ? ly : map_axis(y0 + ly, a.ny, 0, c == 1) - y0;
+          const int sidx = (mx != lx || my != ly) ? (my + 2) * W2 + mx + 2 : -1;
+          if (c == 0)
+            src_x[t] = sidx;
+          else
+            src_y[t] = sidx;
+        }
+      }
+    }
     for (int q = 0; q < a.nodd; ++q) {
       const int4 g = rec4(tab, 4 * q);
-      const int k = rec4(tab, 4 * q + 1).x;
-      for (int e = tid; e < RN; e += kThreads) {
-        const int lx = e % RW - 1, ly = e / RW - 1;
-        const int mx = a.px ? lx : map_axis(x0 + lx, a.nx, 0, g.x == 1) - x0;
-        const int my = a.py ? ly : map_axis(y0 + ly, a.ny, 0, g.y == 1) - y0;
-        if (mx != lx || my != ly) L[k * PL + (ly + 2) * W2 + lx + 2] = L[k * PL + (my + 2) * W2 + mx + 2];
+      const int base = rec4(tab, 4 * q + 1).z;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int sidx = g.x == 1 ? src_x[t] : src_y[t];
+        if (sidx >= 0) L[base + dst[t]] = L[base + sidx];
       }
     }
     __syncthreads();
@@ -271,7 +296,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
 template <typename T>
 size_t lds_t(int nmom, int nd) {
   using C = typename ComputeOf<T>::type;
-  return size_t(nmom) * (32 + 4) * (8 + 4) * sizeof(T) + size_t(nd) * (32 + 4) * (8 + 4) * sizeof(C);
+  return size_t(nmom) * kFusedPlane * sizeof(T) + size_t(nd) * kFusedPlane * sizeof(C);
 }
 
 template <typename T, int B>
@@ -285,7 +310,7 @@ hipError_t launch_b(const FusedArgs& f, hipStream_t stream) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
     if (lds > size_t(max_lds)) return hipErrorInvalidValue;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<T, 32, 8, B>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<T, kFusedTX, kFusedTY, B>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (e != hipSuccess) return e;
     attr = size_t(max_lds);
@@ -304,7 +329,7 @@ hipError_t launch_b(const FusedArgs& f, hipStream_t stream) {
   sc.nd = f.nd;
   sc.tau_odd = C(f.tau_odd);
   sc.tau_even = C(f.tau_even);
-  hipLaunchKernelGGL((fused_kernel<T, 32, 8, B>), dim3(f.ntx * f.nty), dim3(kThreads), lds, stream,
+  hipLaunchKernelGGL((fused_kernel<T, kFusedTX, kFusedTY, B>), dim3(f.ntx * f.nty), dim3(kThreads), lds, stream,
                      static_cast<const T*>(f.uin), static_cast<T*>(f.uout), static_cast<const T*>(f.src),
                      static_cast<const C*>(f.decay), f.tab, static_cast<const C*>(f.coef), sc);
   return hipGetLastError();

@@ -120,6 +120,10 @@ struct FusedScalars {
   int pitch, nx, ny, px, py, ntx, nty, nmom, nodd, nd;
   C tau_odd, tau_even;
 };
+// Tile of the parity-fused pass and its staged plane (two-point halo): the
+// host's coupling table holds LDS offsets in these units.
+constexpr int kFusedTX = 32, kFusedTY = 8;
+constexpr int kFusedRow = kFusedTX + 4, kFusedPlane = kFusedRow * (kFusedTY + 4);
 struct FusedArgs {
   const void* uin;
   void* uout;
