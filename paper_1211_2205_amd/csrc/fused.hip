@@ -10,8 +10,9 @@
 // the grid repeats the nearest grid point, as the separate even sweep's
 // staging map does; on a periodic axis the wrapped staging keeps neighbours
 // adjacent, so ring values are the true ones.  Every point's arithmetic is
-// the separate sweeps' (same coefficients, same order of terms), so the
-// results are bitwise equal.  Neighbouring tiles read each other's halos, so
+// the separate sweeps' (same coefficients, same order of terms; padded
+// coupling terms have coefficient zero), so for finite states the results are
+// bitwise equal.  Neighbouring tiles read each other's halos, so
 // the pass reads one state buffer and writes the other.
 #include "device.hpp"
 #include "kernels.hpp"
@@ -188,7 +189,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
   // before its writes; a moment's update reads only the other parity and its
   // own old value, so the groups of one parity are independent.  Decay factors
   // are cached per grid of the parity (slot: cell centred along x or not).
-  auto update_group = [&](int q0, int qend, int p, const ClassOffsets& co, C tau, DecayCache<C>& dc, bool write) {
+  auto update_group = [&](int q0, int qend, int p, const ClassOffsets& co, C tau, DecayCache<C>& dc) {
     MomentRec r[G];
     C W[G], u[G];
 #pragma unroll
@@ -210,10 +211,8 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
       }
       u[g] = sub_step(u[g], W[g], dc.c(s0), dc.e(s0), tau);
     }
-    if (write) {
 #pragma unroll
-      for (int g = 0; g < G; ++g) L[r[g].n.z + p] = from_c<T>(u[g]);
-    }
+    for (int g = 0; g < G; ++g) L[r[g].n.z + p] = from_c<T>(u[g]);
   };
 
   // 2. odd moments on the tile and its ring (two positions per thread; a
@@ -227,8 +226,8 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
     const ClassOffsets cb = class_offsets(x0 + eb % RW - 1, y0 + eb / RW - 1, a);
     DecayCache<C> da{}, db{};
     for (int q0 = 0; q0 < a.nodd; q0 += G) {
-      update_group(q0, a.nodd, pa, ca, a.tau_odd, da, true);
-      if (has1) update_group(q0, a.nodd, pb, cb, a.tau_odd, db, true);
+      update_group(q0, a.nodd, pa, ca, a.tau_odd, da);
+      if (has1) update_group(q0, a.nodd, pb, cb, a.tau_odd, db);
     }
   }
   __syncthreads();
@@ -275,7 +274,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
   {
     const ClassOffsets ct = class_offsets(x0 + tx, y0 + ty, a);
     DecayCache<C> dt{};
-    for (int q0 = a.nodd; q0 < a.nmom; q0 += G) update_group(q0, a.nmom, pt, ct, a.tau_even, dt, true);
+    for (int q0 = a.nodd; q0 < a.nmom; q0 += G) update_group(q0, a.nmom, pt, ct, a.tau_even, dt);
   }
   __syncthreads();
 
