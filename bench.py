@@ -78,8 +78,14 @@ def cpu_baseline(prob, rows):
     scheme.set_threads(1)
     v1, sample1 = run(rows)
     scheme.set_threads(all_threads)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": v, "unit": "cell-moment updates/s", "cores": all_threads, "kind": "oracle",
-            "sample": sample,
+            "cpu_model": model, "sample": sample,
             "single_thread": {"value": v1, "unit": "cell-moment updates/s", "cores": 1, "sample": sample1}}
 
 
@@ -220,8 +226,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design note, not code)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the decomposition over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
