@@ -45,6 +45,9 @@ CASES = [
     ("random3_mixed", lambda: wl.random_medium(52, 3, 40, t_final=0.3), (33, 66), (P, X)),
     ("random1_mixed", lambda: wl.random_medium(53, 1, 40, t_final=0.3), (31, 29), (X, P)),
     ("line2", lambda: wl.line_source(N=2, n=50, s=0.1, half_width=1.0, t_final=0.3), (50, 50), (X, X)),
+    # smaller than one 32 x 8 tile, and exactly one tile of points (nx + 1 = 32, ny + 1 = 8)
+    ("tiny4_mixed", lambda: wl.random_medium(54, 4, 10, t_final=1.0), (7, 5), (X, P)),
+    ("tile_edge6", lambda: wl.random_medium(55, 6, 10, t_final=0.2), (31, 7), (P, X)),
 ]
 
 
