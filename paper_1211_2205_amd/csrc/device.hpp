@@ -20,6 +20,18 @@ __device__ __forceinline__ double to_c(double v) { return v; }
 __device__ __forceinline__ float to_c(float v) { return v; }
 __device__ __forceinline__ float to_c(bf16 v) { return __uint_as_float(uint32_t(v.bits) << 16); }
 
+// Type of a staged LDS window: the storage type, except that BF16 values are
+// widened to FP32 when staged (16-bit LDS accesses cannot be paired and their
+// writes share dwords; the widening is exact).
+template <typename T>
+struct StagedOf {
+  using type = T;
+};
+template <>
+struct StagedOf<bf16> {
+  using type = float;
+};
+
 template <typename T> __device__ __forceinline__ T from_c(typename ComputeOf<T>::type v);
 template <> __device__ __forceinline__ double from_c<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_c<float>(float v) { return v; }

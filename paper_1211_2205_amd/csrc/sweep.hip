@@ -77,8 +77,9 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
                                            cptr<typename ComputeOf<T>::type> rcoef,
                                            const SweepScalars<typename ComputeOf<T>::type>& a, const int lb) {
   using C = typename ComputeOf<T>::type;
+  using S = typename StagedOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* L = reinterpret_cast<T*>(smem);
+  S* L = reinterpret_cast<S*>(smem);
   constexpr int LW = TX + 1;
   constexpr int P = (TX + 1) * (TY + 1);
   constexpr int NP = TX * TY;
@@ -199,7 +200,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
           const int4 ld = rec4(loads, first + bb + b);
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
-            if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = v[b][q];
+            if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(to_c(v[b][q]));
         }
       }
     }
@@ -269,7 +270,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   };
 
   // the padding couplings read this plane of zeros
-  for (int e = tid; e < P; e += 256) L[a.zero_off + e] = from_c<T>(C(0));
+  for (int e = tid; e < P; e += 256) L[a.zero_off + e] = S(0);
   // prologue: the first window and the first rows
   C ua[RB][PPT];
   {
@@ -324,12 +325,12 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
             C W = C(0);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-              const T* lp = L + rec[4 + t] + pos[p];
+              const S* lp = L + rec[4 + t] + pos[p];
               W = couple(W, cf[t], to_c(lp[1]), to_c(lp[0]));
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-              const T* lp = L + rec[8 + t] + pos[p];
+              const S* lp = L + rec[8 + t] + pos[p];
               W = couple(W, cf[4 + t], to_c(lp[LW]), to_c(lp[0]));
             }
     // the source, staged in LDS, joins the residual
@@ -352,7 +353,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const int4 ld = rec4(loads, nxt.x + b);
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
-          if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = stg[b][q];
+          if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(to_c(stg[b][q]));
       }
     }
     if (nl > MAXP) stage_sync(nxt.x, MAXP, nl);
@@ -477,7 +478,7 @@ hipError_t prepare_t(size_t lds) {
 
 template <typename T, int TX, int TY, int CAP>
 size_t lds_t(int slots) {
-  return size_t(slots) * (TX + 1) * (TY + 1) * sizeof(T);
+  return size_t(slots) * (TX + 1) * (TY + 1) * sizeof(typename StagedOf<T>::type);
 }
 
 template <typename T, int TX, int TY, int CAP>
@@ -566,7 +567,7 @@ TileShape sweep_variant(int v) { return kVariants[v]; }
 
 
 size_t sweep_lds_bytes(int v, int slots, int storage) {
-  const size_t s = storage == STORE_FP64 ? 8 : storage == STORE_FP32 ? 4 : 2;
+  const size_t s = storage == STORE_FP64 ? 8 : 4;  // BF16 windows are staged as FP32
   return size_t(slots) * (kVariants[v].tx + 1) * (kVariants[v].ty + 1) * s;
 }
 
