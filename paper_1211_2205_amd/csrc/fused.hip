@@ -100,8 +100,9 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
   static_assert(PL == kFusedPlane && W2 == kFusedRow, "the host's coupling offsets use the same staged plane");
   static_assert(RN <= 2 * kThreads, "tile and ring within two points per thread");
   extern __shared__ __align__(16) unsigned char smem[];
-  T* L = reinterpret_cast<T*>(smem);                                   // nmom planes of PL
-  C* D = reinterpret_cast<C*>(smem + size_t(a.nmom) * PL * sizeof(T));  // nd decay planes of PL
+  using S = typename StagedOf<T>::type;                                // BF16 staged as FP32
+  S* L = reinterpret_cast<S*>(smem);                                   // nmom planes of PL
+  C* D = reinterpret_cast<C*>(smem + size_t(a.nmom) * PL * sizeof(S));  // nd decay planes of PL
   const cptr<int> tab = (cptr<int>)tab_arg;
   const cptr<C> coef = (cptr<C>)coef_arg;
   const int tid = threadIdx.x;
@@ -149,7 +150,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
 #pragma unroll
           for (int q = 0; q < E; ++q) {
             const int e = tid + q * kThreads;
-            if (e < PL) L[k * PL + e] = v[b][q];
+            if (e < PL) L[k * PL + e] = S(to_c(v[b][q]));
           }
         }
       }
@@ -212,7 +213,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
       u[g] = sub_step(u[g], W[g], dc.c(s0), dc.e(s0), tau);
     }
 #pragma unroll
-    for (int g = 0; g < G; ++g) L[r[g].n.z + p] = from_c<T>(u[g]);
+    for (int g = 0; g < G; ++g) L[r[g].n.z + p] = S(to_c(from_c<T>(u[g])));  // rounded to the storage type
   };
 
   // 2. odd moments on the tile and its ring (two positions per thread; a
@@ -287,7 +288,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
     for (int q = 0; q < a.nmom; ++q) {
       const int4 g = rec4(tab, 4 * q);
       const int k = rec4(tab, 4 * q + 1).x;
-      if ((g.x == 1 ? in_x1 : in_x0) && (g.y == 1 ? in_y1 : in_y0)) plane_at(uout, k, ps)[off] = L[k * PL + pt];
+      if ((g.x == 1 ? in_x1 : in_x0) && (g.y == 1 ? in_y1 : in_y0)) plane_at(uout, k, ps)[off] = from_c<T>(to_c(L[k * PL + pt]));
     }
   }
 }
@@ -295,7 +296,7 @@ fused_kernel(const T* __restrict__ uin, T* __restrict__ uout, const T* __restric
 template <typename T>
 size_t lds_t(int nmom, int nd) {
   using C = typename ComputeOf<T>::type;
-  return size_t(nmom) * kFusedPlane * sizeof(T) + size_t(nd) * kFusedPlane * sizeof(C);
+  return size_t(nmom) * kFusedPlane * sizeof(typename StagedOf<T>::type) + size_t(nd) * kFusedPlane * sizeof(C);
 }
 
 template <typename T, int B>
