@@ -36,11 +36,8 @@ template <typename T> __device__ __forceinline__ T from_c(typename ComputeOf<T>:
 template <> __device__ __forceinline__ double from_c<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_c<float>(float v) { return v; }
 template <> __device__ __forceinline__ bf16 from_c<bf16>(float v) {
-  // round to nearest even; NaN stays NaN
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return bf16{uint16_t((u >> 16) | 0x40u)};
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return bf16{uint16_t(u >> 16)};
+  // round to nearest even (the hardware conversion); NaN stays NaN
+  return bf16{__builtin_bit_cast(uint16_t, static_cast<__bf16>(v))};
 }
 
 __device__ __forceinline__ double expm1_c(double z) { return expm1(z); }
