@@ -2,7 +2,8 @@
 """Throughput of the staggered-grid P_N step on one MI355X.
 
 Default workload: the large line source (P_39, 820 moments, 1000 x 1000
-cells, FP32 storage, CFL 0.5, t_final = 1: 666 steps).  A step is one full
+cells, FP64 storage as in the paper, CFL 0.5, t_final = 1: 666 steps), with
+FP32 and BF16 storage as further legs.  A step is one full
 time step of every moment (odd and even parity sweeps); the first `warmup`
 steps of the run are untimed and the remaining `steps` are timed, so the
 default covers exactly the run to t_final.
@@ -29,6 +30,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_line_source_P39_1000_{}_pmc.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_1211_2205_amd", "csrc", "sweep.hip")
+SIZE = {"fp64": 8, "fp32": 4, "bf16": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 
 
 def _sweep_source_hash():
@@ -36,19 +39,35 @@ def _sweep_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(launch_bytes, precision):
-    """HBM bytes per launch from the committed PMC summary, if it was taken on
-    the current sweep kernel source; else None."""
+def _pmc_record(precision, workload):
+    """The committed HBM-counter summary of the sweep kernel for this workload
+    and precision, if it was taken on the current kernel source; else None."""
     try:
         with open(PMC_SUMMARY.format(precision)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("sweep_source_sha256_16") != _sweep_source_hash() or rec.get("precision") != precision:
+    if (rec.get("sweep_source_sha256_16") != _sweep_source_hash() or rec.get("precision") != precision
+            or rec.get("workload") != workload or "parity" not in rec):
         return None
-    if abs(rec.get("algorithmic_bytes_per_launch", 0.0) - launch_bytes) > 1e-6 * launch_bytes:
-        return None  # counters taken on another workload
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def _traffic(rec, variant, width, n_odd, n_even, alg_odd, alg_even):
+    """HBM bytes per launch of this run, composed from the counter runs of each
+    parity (one parity per counter run) with this run's own mix of odd and
+    even launches; None unless the counters were taken on the same tile
+    variant, m-range width and per-parity algorithmic bytes."""
+    if rec is None or rec.get("variant") != variant or rec.get("width") != width:
+        return None
+    odd, even = rec["parity"].get("odd"), rec["parity"].get("even")
+    if not odd or not even:
+        return None
+    for r, alg in ((odd, alg_odd), (even, alg_even)):
+        if abs(r["algorithmic_bytes_per_launch"] - alg) > 1e-9 * alg:
+            return None
+    n = n_odd + n_even
+    return (n_odd * odd["hbm_bytes_per_launch"] + n_even * even["hbm_bytes_per_launch"]) / n
 
 
 def cpu_baseline(prob, rows):
@@ -204,14 +223,179 @@ def fused_leg(N, n, precision, steps):
     return out
 
 
+def _tile_for(prec, workload, variant, width):
+    """(variant, width) for the run: as given, else the pair the committed
+    counter summary was taken on (the autotuner's choice when it was made, on
+    the same kernel source), else None (autotune)."""
+    if variant is not None:
+        return variant, width
+    rec = _pmc_record(prec, workload)
+    if rec is not None:
+        return rec["variant"], rec["width"]
+    return None, width
+
+
+def timed_run(prob, steps, warmup, variant=None, width=None):
+    """One solver on prob: warmup untimed steps, then `steps` timed steps
+    (wall clock around the advance call, and HIP events around every sweep
+    launch on the solver's stream).  Returns the open solver and the record
+    (value, roofline).  Keeps the solver at step warmup + steps."""
+    import torch
+
+    import paper_1211_2205_amd as pa
+    prec = prob.precision
+    workload = f"{prob.name}_{prec}"
+    variant, width = _tile_for(prec, workload, variant, width)
+    s = pa.Solver.from_problem(prob)
+    s.bind_torch()
+    if variant is None:
+        s.autotune(2)
+    else:
+        if width:
+            s.set_chunk_width(width)
+        s.set_variant(variant)
+    total = s.nsteps
+    warm = max(0, min(warmup, total - 1))
+    steps = total - warm if steps is None else min(steps, total - warm)
+    nx, ny = prob.n
+    s.advance(warm)
+    s.synchronize()
+    torch.cuda.synchronize()
+    s.profile_begin()
+    t0 = time.perf_counter()
+    s.advance(steps)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms, launches, alg_bytes = s.profile_end()
+    wall = t1 - t0
+    v, tx, ty = s.variant()
+    w = s.chunk_width()
+    # plain P_N, time-independent data: one advance of k steps launches the odd
+    # sweep k + 1 times and the even sweep k times
+    n_odd, n_even = steps + 1, steps
+    b_odd, b_even = s.sweep_bytes(1), s.sweep_bytes(0)
+    assert launches == n_odd + n_even and abs(n_odd * b_odd + n_even * b_even - alg_bytes) <= 1e-9 * alg_bytes
+    updates = nx * ny * s.nmom * steps
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    per_launch = alg_bytes / launches
+    avg_ms = kernel_ms / launches
+    traffic = _traffic(_pmc_record(prec, workload), v, w, n_odd, n_even, b_odd, b_even)
+    rec = {
+        "value": updates / wall, "unit": "cell-moment updates/s", "steps": steps, "warmup": warm,
+        "ms_per_step": wall / steps * 1e3, "dtype": DTYPE[prec],
+        "config": {"workload": workload, "N": prob.N, "moments": s.nmom, "cells": [nx, ny],
+                   "t_final": prob.t_final, "steps_to_t_final": total, "tile": [tx, ty], "variant": v,
+                   "m_range_width": w, "sweeps_timed": launches, "odd_sweeps": n_odd, "even_sweeps": n_even},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "sweep_kernel", "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": per_launch,
+                     "algorithmic_bytes_odd": b_odd, "algorithmic_bytes_even": b_even,
+                     # HBM bytes of the counter runs over this run's launch time,
+                     # the ratio of HBM to algorithmic bytes, and the design's
+                     # 3 s bytes per cell-moment update at the measured rate
+                     "hbm_GBs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_over_algorithmic": traffic / per_launch if traffic else None,
+                     "effective_GBs": 3 * SIZE[prec] * updates / wall / 1e9},
+    }
+    return s, rec
+
+
+def compare_states(a, b):
+    """a against b (same problem, another storage precision), moment by
+    moment through get_moment: relative L2 over all moments and points, the
+    worst moment's relative L2 (its error over max(its norm, 1% of the largest
+    moment norm)), and the largest pointwise error over max |b|."""
+    num = den = 0.0
+    errs, norms = [], []
+    elem = scale = 0.0
+    for k in range(b.nmom):
+        gb = b.get_moment(k)
+        d = a.get_moment(k) - gb
+        e2, n2 = float((d * d).sum()), float((gb * gb).sum())
+        num += e2
+        den += n2
+        errs.append(math.sqrt(e2))
+        norms.append(math.sqrt(n2))
+        elem = max(elem, float(abs(d).max()))
+        scale = max(scale, float(abs(gb).max()))
+    floor = 1e-2 * max(norms)
+    per = [e / max(n, floor) for e, n in zip(errs, norms)]
+    k = max(range(len(per)), key=per.__getitem__)
+    return {"rel_l2": math.sqrt(num / den), "worst_moment": k, "worst_moment_rel_l2": per[k],
+            "max_element_rel": elem / scale}
+
+
+def ceiling_leg(gib):
+    """Streaming ceilings of the device with plain library kernels (torch's
+    own, on torch's current stream, timed with its events): a copy (1 read,
+    1 write) and an elementwise add of two arrays into a third (2 reads, 1
+    write: the sweep's mix of input, output-read and output-write bytes)."""
+    import torch
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.full_like(a, 2.0)
+    c = torch.empty_like(a)
+    out = {"bytes_per_array": 8 * n}
+    for name, fn, nbytes in (("copy", lambda: c.copy_(a), 16 * n), ("add", lambda: torch.add(a, b, out=c), 24 * n)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
+def sweep_only(prob, parity, sweeps, variant, width):
+    """Counter runs: `sweeps` single sweeps of one parity (tau = dt) on the
+    workload's initial state, nothing else launched on the solver's stream
+    after setup.  Prints the parity's algorithmic bytes per launch."""
+    import torch
+
+    import paper_1211_2205_amd as pa
+    s = pa.Solver.from_problem(prob)
+    s.bind_torch()
+    if width:
+        s.set_chunk_width(width)
+    s.set_variant(variant)
+    s.synchronize()
+    torch.cuda.synchronize()
+    p = 1 if parity == "odd" else 0
+    s.sweep(p, s.dt, sweeps)
+    s.synchronize()
+    v, tx, ty = s.variant()
+    print(json.dumps({"workload": f"{prob.name}_{prob.precision}", "parity": parity, "sweeps": sweeps,
+                      "variant": v, "width": s.chunk_width(), "tile": [tx, ty],
+                      "algorithmic_bytes_per_launch": s.sweep_bytes(p),
+                      "sweep_source_sha256_16": _sweep_source_hash()}), flush=True)
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the rest of the run)")
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
-    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--variant", type=int, default=None, help="sweep tile variant (default: autotune)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--legs", default="fp32,bf16",
+                    help="further storage precisions timed on the same workload, each with its own roofline "
+                         "and its error against the headline's state at t_final (comma-separated; '' for none)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="sweep tile variant (default: the one of the committed counter summary, else autotune)")
+    ap.add_argument("--width", type=int, default=None, help="m-range width with --variant")
     ap.add_argument("--cpu-rows", type=int, default=200, help="rows of the oracle's CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0: skip it)")
@@ -221,8 +405,13 @@ def main():
     ap.add_argument("--fused-cells", default="1000,2048", help="grid sizes n (n x n) of the parity-fused leg")
     ap.add_argument("--models-steps", type=int, default=20,
                     help="timed steps of the FP_N / D_N model leg (0: skip it)")
+    ap.add_argument("--ceiling-gib", type=float, default=2.0,
+                    help="array size of the streaming-ceiling leg (torch copy and add; 0: skip it)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a device copy of this size (HBM counter calibration) and exit")
+    ap.add_argument("--sweep-only", choices=["odd", "even"], default=None,
+                    help="only run --sweeps sweeps of one parity (HBM counter runs) and exit")
+    ap.add_argument("--sweeps", type=int, default=8)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -245,75 +434,61 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
         return
 
-    import paper_1211_2205_amd as pa
     import workloads as wl
 
     prob = wl.config(args.config, precision=args.precision)
-    prec = prob.precision
-    s = pa.Solver.from_problem(prob)
-    s.bind_torch()
-    if args.variant is None:
-        s.autotune(2)
-    else:
-        s.set_variant(args.variant)
-    total = s.nsteps
-    warm = max(0, min(args.warmup, total - 1))
-    steps = args.steps if args.steps is not None else total - warm
-    nmom = s.nmom
-    nx, ny = prob.n
+    if args.sweep_only:
+        variant, width = _tile_for(prob.precision, f"{prob.name}_{prob.precision}", args.variant, args.width)
+        if variant is None:
+            print("bench.py: --sweep-only needs --variant (and --width)", file=sys.stderr)
+            sys.exit(2)
+        sweep_only(prob, args.sweep_only, args.sweeps, variant, width)
+        return
 
-    s.advance(warm)
-    s.synchronize()
-    torch.cuda.synchronize()
-    s.profile_begin()
-    t0 = time.perf_counter()
-    s.advance(steps)
-    s.synchronize()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kernel_ms, launches, alg_bytes = s.profile_end()
-    wall = t1 - t0
+    s, head = timed_run(prob, args.steps, args.warmup, args.variant, args.width)
     diag = s.diagnostics()
-
-    updates = nx * ny * nmom * steps
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    per_launch = alg_bytes / launches
-    v, tx, ty = s.variant()
-    traffic = _traffic(per_launch, prec)
     out = {
         "metric": "cell-moment updates/s",
-        "value": updates / wall,
+        "value": head["value"],
         "unit": "cell-moment updates/s",
         "n_gpus": 1,
-        "steps": steps,
-        "warmup": warm,
-        "ms_per_step": wall / steps * 1e3,
+        "steps": head["steps"],
+        "warmup": head["warmup"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec],
+        "dtype": head["dtype"],
         "data": "synthetic",
-        "config": {"workload": f"{prob.name}_{prec}", "N": prob.N, "moments": nmom, "cells": [nx, ny],
-                   "t_final": prob.t_final, "steps_to_t_final": total, "tile": [tx, ty],
-                   "sweeps_timed": launches},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": "sweep_kernel", "avg_launch_ms": kernel_ms / launches,
-                     "algorithmic_bytes_per_launch": per_launch,
-                     # HBM bytes of the counter runs over this run's launch time, and
-                     # the design's 3 s bytes per cell-moment update at the measured rate
-                     "hbm_GBs": traffic / (kernel_ms / launches * 1e-3) / 1e9 if traffic else None,
-                     "effective_GBs": 3 * {"fp64": 8, "fp32": 4, "bf16": 2}[prec] * updates / wall / 1e9},
+        "config": head["config"],
+        "roofline": head["roofline"],
         "state_check": {"mass": diag["mass"], "l2": diag["l2"], "nonfinite": diag["nonfinite"]},
     }
+    legs = [p for p in args.legs.split(",") if p and p != prob.precision]
+    if legs:
+        # every leg runs on to t_final (untimed) and is compared with the
+        # headline run's state there
+        s.advance(s.nsteps - s.time()[2])
+        s.synchronize()
+        out["precisions"] = {}
+        for prec in legs:
+            lp = wl.config(args.config, precision=prec)
+            ls, rec = timed_run(lp, args.steps, args.warmup, None if args.variant is None else args.variant,
+                                args.width)
+            ls.advance(ls.nsteps - ls.time()[2])
+            ls.synchronize()
+            rec["against_" + prob.precision + "_at_t_final"] = compare_states(ls, s)
+            ls.close()
+            out["precisions"][prec] = rec
     s.close()
+    if args.ceiling_gib > 0:
+        out["ceiling"] = ceiling_leg(args.ceiling_gib)
     if args.models_steps > 0:
-        out["models"] = models_leg(args.config, prec, args.models_steps)
+        out["models"] = models_leg(args.config, prob.precision, args.models_steps)
     if args.fused_steps > 0:
         # 1000^2: one state copy (144 MB in FP32) stays in the 256 MB last-level
         # cache; 2048^2 (604 MB) does not
-        out["fused"] = [fused_leg(int(N), int(n), prec, args.fused_steps)
+        out["fused"] = [fused_leg(int(N), int(n), prob.precision, args.fused_steps)
                         for N in args.fused_orders.split(",") for n in args.fused_cells.split(",")]
     if args.batch > 0:
         out["batch"] = batch_leg(args.batch, "fp32")

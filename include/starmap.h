@@ -117,7 +117,7 @@ int starmap_moment_info(int32_t N, int32_t k, int32_t* is_imag, int32_t* l, int3
 int starmap_closure_pn(int32_t N, int32_t axis, int32_t* cols, double* vals);
 
 /* Largest eigenvalue magnitude of M_x of order N (the maximal wave speed that
-   scales the admissible time step, Sect. 4.6 and Sect. 5.3). */
+   scales the admissible time step, Sect. 4.5 and Sect. 5.3). */
 int starmap_spectral_radius(int32_t N, double* rho);
 
 /* Moments of a unit beam source delta(Omega - Omega_0) in direction
@@ -145,7 +145,7 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out);
 void starmap_destroy(starmap_solver* s);
 
 /* Material and source fields, sampled on the host in FP64 at each grid's
-   points when the solver first needs them (Sect. 5.6).  Isotropic scattering
+   points when the solver first needs them (Sect. 5.7).  Isotropic scattering
    uses sigma_s0 only: moments of order l >= 1 decay with sigma_a + sigma_s0,
    the zeroth moment with sigma_a (Sect. 2: Sigma_tl = Sigma_a + Sigma_s0 -
    Sigma_sl).  Missing fields are zero.  time_dependent != 0 re-samples the
@@ -240,6 +240,15 @@ int starmap_set_variant(starmap_solver* s, int32_t variant);
 int starmap_get_variant(const starmap_solver* s, int32_t* variant, int32_t* tile_x, int32_t* tile_y);
 int starmap_autotune(starmap_solver* s, int32_t sweeps_per_variant);
 
+/* Width of the m ranges the sweep splits the outputs of one order into (an
+   output (l, m) couples only to inputs (l -+ 1, m -+ 1), Lemma 2): 4, 6 or 8
+   (another value: STARMAP_EINVAL; the default is 8, or the autotuner's or
+   the tune cache's choice).  All widths give the same bits.  A width at
+   which the current tile variant no longer fits the LDS fails with
+   STARMAP_EINVAL and leaves the width unchanged. */
+int starmap_set_range_width(starmap_solver* s, int32_t width);
+int starmap_get_range_width(const starmap_solver* s, int32_t* width);
+
 /* Bytes the sweep kernel moves per parity sweep by the algorithm's count:
    every input plane read once, every output plane read and written once, plus
    the decay and source planes it reads (valid points only). */
@@ -268,9 +277,10 @@ int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches,
        moment's array, divided by nu = sqrt(sum of their squares) + 1e-20;
        then log10(sigma_a + 0.01) and log10(sigma_s + 0.01) at the G11 cell
        (min(i, nx-1), min(j, ny-1)); then zeros;
-     - network y = W3 gelu(W2 gelu(W1 x + b1) + b2) + b3 (128, 128, 6 units,
-       exact-erf GELU), matrix-product operands rounded to bfloat16, FP32
-       accumulation;
+     - network y = W3 gelu(W2 gelu(W1 x + b1) + b2) + b3 (128, 128, 6 units;
+       gelu(z) = z Phi(z) with the erf of Abramowitz & Stegun formula 7.1.26,
+       |error| <= 1.5e-7, in inference and in the trainer below alike),
+       matrix-product operands rounded to bfloat16, FP32 accumulation;
      - closure term of output r (R_5^5, I_5^5, R_5^3, I_5^3, R_5^1, I_5^1):
        g_r = nu * y_r / dx.
    The term is evaluated on the state at the start of each odd sweep and held
@@ -325,7 +335,7 @@ int starmap_mlp_train_step(starmap_mlp* n, const float* x, const float* t, int32
 int starmap_mlp_adam_step(starmap_mlp* n, const float* grad_host, double lr);
 
 /* Time-separable fields evaluated on the device (time-dependent data,
-   Sect. 5.6).  Adds a term a(t) g(x, y) to a field: which =
+   Sect. 5.7).  Adds a term a(t) g(x, y) to a field: which =
    STARMAP_FIELD_ABSORPTION, STARMAP_FIELD_SCATTERING,
    STARMAP_FIELD_SCATTERING_ORDER (index = order l, 1 <= l <= N) or
    STARMAP_FIELD_SOURCE (index = moment k).  A field given by terms is

@@ -13,7 +13,7 @@ radiative transfer" (arXiv 1211.2205):
   * slab matrix ...................... Sect. 2 (eq. PN_slab)
   * grid classes ..................... Sect. 4.1 (eq. matrix_conditions) and
                                        the greedy assignment of Sect. 5.3
-  * time step ........................ Sect. 4.4 (Thm. 1 and the rules after it)
+  * time step ........................ Sect. 4.5 (Thm. 1 and the rules after it)
 """
 from __future__ import annotations
 

@@ -5,8 +5,8 @@ baseline may use anything under oracle/.  The product path never does.
 
 The time loop is the paper's literal composition (eq. solution_operator_full_step):
 per step, evaluate materials and sources at t + dt/2 (once if time-independent,
-Sect. 5.6), then S^o_{dt/2}, compute the even residual once, S^e_{dt/2} twice with
-it (Sect. 5.7), recompute the odd residual, S^o_{dt/2}.  The optional `fused`
+Sect. 5.7), then S^o_{dt/2}, compute the even residual once, S^e_{dt/2} twice with
+it (Sect. 5.8), recompute the odd residual, S^o_{dt/2}.  The optional `fused`
 composition instead applies S^o_{dt/2}, [S^e_{dt}, S^o_{dt}]^(n-1), S^e_{dt},
 S^o_{dt/2}; with frozen data both compositions are equal in exact arithmetic.
 
@@ -163,7 +163,7 @@ class OracleSolver:
     def evaluate_materials(self, t):
         """Decay c_k and source q_k on each component's grid at time t:
         c = sigma_a for the zeroth moment, c = sigma_a + sigma_s0 - sigma_sl for
-        order l >= 1 (Sect. 2: Sigma_tl; Sect. 5.4); q only on the components the
+        order l >= 1 (Sect. 2: Sigma_tl; Sect. 5.5); q only on the components the
         problem lists."""
         prob = self.prob
         c, q = [], []

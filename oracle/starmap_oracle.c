@@ -15,8 +15,8 @@
  *     (eq. hyperbolic_balance_law_decoupled) and the exact sub-step solution
  *     u <- u + tau (r - c u) E(-c tau), E(z) = (e^z - 1)/z (eq. sub_step_solution).
  *
- * Plain loops; OpenMP only splits independent rows, so results are identical
- * for any thread count.
+ * Plain loops; OpenMP only splits independent rows (one parallel region per
+ * call), so results are identical for any thread count.
  */
 #include <math.h>
 #include <omp.h>
@@ -29,7 +29,7 @@ static int npts(int type, int n, int p) { return type == 1 ? n : n + 1 - p; }
 
 /* E(z) = (exp(z) - 1) / z, E(0) = 1.
    mode 0: expm1(z) / z.
-   mode 1: the paper's switch (Sect. 5.5): a three-term Taylor series below
+   mode 1: the paper's switch (Sect. 5.6): a three-term Taylor series below
            |z| <= 2e-4, else the plain quotient.  The series used is that of
            E itself, 1 + z/2 + z^2/6 (the printed series has the sign of the
            linear term flipped, i.e. it is the series of E(-z)). */
@@ -51,69 +51,41 @@ void starmap_oracle_set_threads(int n) {
 int starmap_oracle_threads(void) { return omp_get_max_threads(); }
 
 /*
- * D_x of a field on grid (tx, ty) -> field on grid (3 - tx, ty).
- * The source row is first extended by the boundary rule, then differenced:
- *   tx == 1 (cells 1..n, result on nodes p..n): extended cells p..n+1 with
- *           ghost cell 0 := cell 1 (extrapolation) and ghost cell n+1 := cell n
- *           (extrapolation) or := cell 1 (periodic);
- *   tx == 2 (nodes p..n, result on cells 1..n): extended nodes 0..n with
- *           node 0 := node n (periodic); extrapolation has node 0 already.
- * Result(a) = (ext(a+1) - ext(a)) / h for a = 0 .. (result points - 1).
+ * Boundary extension (Sect. 4.2) along one axis: the stored index of the
+ * value at extended position a of a field of type `type` (1 = cell centres,
+ * 2 = nodes) with n cells and periodicity flag p.  The difference onto the
+ * other type at position a is (ext(a+1) - ext(a)) / h.
+ *   type 1 (cells 1..n stored at 0..n-1, result on nodes p..n): extended
+ *          cells p..n+1; ghost cell 0 := cell 1 (extrapolation; reached only
+ *          when p = 0), ghost cell n+1 := cell n (extrapolation) or cell 1
+ *          (periodic);
+ *   type 2 (nodes p..n stored at 0..n-p, result on cells 1..n): extended
+ *          nodes 0..n; node 0 := node n (periodic); extrapolation stores
+ *          node 0 itself.
  */
-static void diff_x(int tx, int ty, int nx, int ny, int px, int py, double dx,
-                   const double* src, double* dst) {
-    const int ns = npts(tx, nx, px);
-    const int nd = npts(3 - tx, nx, px);
-    const int rows = npts(ty, ny, py);
-#pragma omp parallel for schedule(static)
-    for (int j = 0; j < rows; ++j) {
-        const double* s = src + (size_t)j * ns;
-        double* d = dst + (size_t)j * nd;
-        double* ext = (double*)malloc(sizeof(double) * (size_t)(nd + 1));
-        for (int a = 0; a <= nd; ++a) {
-            double v;
-            if (tx == 1) {
-                int ci = px + a;                     /* paper cell index, 0..n+1 */
-                if (ci == 0) v = s[0];               /* ghost left (extrapolation) */
-                else if (ci == nx + 1) v = px ? s[0] : s[nx - 1];
-                else v = s[ci - 1];
-            } else {
-                int ni = a;                          /* paper node index 0..n */
-                if (ni == 0 && px) v = s[nx - 1];    /* node 0 := node n (periodic) */
-                else v = s[ni - px];
-            }
-            ext[a] = v;
-        }
-        for (int a = 0; a < nd; ++a) d[a] = (ext[a + 1] - ext[a]) / dx;
-        free(ext);
+static int ext_index(int type, int a, int n, int p) {
+    if (type == 1) {
+        int ci = p + a;              /* paper cell index, 0..n+1 */
+        if (ci == 0) return 0;       /* ghost left := cell 1 */
+        if (ci == n + 1) return p ? 0 : n - 1;
+        return ci - 1;
     }
+    if (a == 0 && p) return n - 1;   /* node 0 := node n */
+    return a - p;
 }
 
-/* D_y: the same rule along y; field on grid (tx, ty) -> grid (tx, 3 - ty). */
-static void diff_y(int tx, int ty, int nx, int ny, int px, int py, double dy,
-                   const double* src, double* dst) {
-    const int cols = npts(tx, nx, px);
-    const int nd = npts(3 - ty, ny, py);
-#pragma omp parallel for schedule(static)
-    for (int i = 0; i < cols; ++i) {
-        double* ext = (double*)malloc(sizeof(double) * (size_t)(nd + 1));
-        for (int a = 0; a <= nd; ++a) {
-            double v;
-            if (ty == 1) {
-                int ci = py + a;
-                if (ci == 0) v = src[i];
-                else if (ci == ny + 1) v = py ? src[i] : src[(size_t)(ny - 1) * cols + i];
-                else v = src[(size_t)(ci - 1) * cols + i];
-            } else {
-                int ni = a;
-                if (ni == 0 && py) v = src[(size_t)(ny - 1) * cols + i];
-                else v = src[(size_t)(ni - py) * cols + i];
-            }
-            ext[a] = v;
-        }
-        for (int a = 0; a < nd; ++a) dst[(size_t)a * cols + i] = (ext[a + 1] - ext[a]) / dy;
-        free(ext);
-    }
+/* Row y of D_x: field on grid (tx, .) with rows of ns values -> nd values. */
+static void diff_x_row(int tx, int nx, int px, double dx, const double* s, double* d) {
+    const int nd = npts(3 - tx, nx, px);
+    for (int a = 0; a < nd; ++a)
+        d[a] = (s[ext_index(tx, a + 1, nx, px)] - s[ext_index(tx, a, nx, px)]) / dx;
+}
+
+/* Row a of D_y: field on grid (., ty) with `cols` values a row. */
+static void diff_y_row(int ty, int ny, int py, double dy, int cols, const double* src, int a, double* d) {
+    const double* hi = src + (size_t)ext_index(ty, a + 1, ny, py) * (size_t)cols;
+    const double* lo = src + (size_t)ext_index(ty, a, ny, py) * (size_t)cols;
+    for (int i = 0; i < cols; ++i) d[i] = (hi[i] - lo[i]) / dy;
 }
 
 static size_t plane_size(const int* gx, const int* gy, int k, int nx, int ny, int px, int py) {
@@ -123,54 +95,76 @@ static size_t plane_size(const int* gx, const int* gy, int k, int nx, int ny, in
 /*
  * W_k = - sum_j Mx(k,j) D_x u_j - sum_j My(k,j) D_y u_j for every component k
  * of the given parity (even: G11 and G22; odd: G21 and G12).  Only the nonzero
- * entries of the rows are visited.  W[k] must hold k's grid size for those k.
- * Returns 0, or -1 if a nonzero entry couples grids that the staggering does
- * not allow.
+ * entries of the rows are visited, j ascending, the x term before the y term.
+ * W[k] must hold k's grid size for those k.  Returns 0, or -1 if a nonzero
+ * entry couples grids that the staggering does not allow.
+ *
+ * One parallel region: first the differences of every component of the other
+ * parity (rows split over threads), then every output row; each point's
+ * arithmetic is the same for any thread count.
  */
 int starmap_oracle_flux(int nx, int ny, int px, int py, double dx, double dy, int nmom,
                         const int* gx, const int* gy, const double* Mx, const double* My,
                         int parity, double* const* u, double* const* W) {
-    /* differences of all components of the other parity, computed once each */
+    if (nmom <= 0) return -1;
+    /* the coupling pattern must match the staggering (checked up front) */
+    for (int k = 0; k < nmom; ++k) {
+        int even_k = gx[k] == gy[k];
+        if ((parity == 0) != even_k) continue;
+        for (int j = 0; j < nmom; ++j) {
+            int other = (gx[j] == gy[j]) != even_k;
+            if (Mx[(size_t)k * nmom + j] != 0.0 && (!other || 3 - gx[j] != gx[k] || gy[j] != gy[k])) return -1;
+            if (My[(size_t)k * nmom + j] != 0.0 && (!other || gx[j] != gx[k] || 3 - gy[j] != gy[k])) return -1;
+        }
+    }
     double** DX = (double**)calloc((size_t)nmom, sizeof(double*));
     double** DY = (double**)calloc((size_t)nmom, sizeof(double*));
-    int status = 0;
     for (int j = 0; j < nmom; ++j) {
         int even_j = gx[j] == gy[j];
         if ((parity == 0) == even_j) continue;  /* same parity as the outputs */
-        size_t szx = (size_t)npts(3 - gx[j], nx, px) * (size_t)npts(gy[j], ny, py);
-        size_t szy = (size_t)npts(gx[j], nx, px) * (size_t)npts(3 - gy[j], ny, py);
-        DX[j] = (double*)malloc(sizeof(double) * szx);
-        DY[j] = (double*)malloc(sizeof(double) * szy);
-        diff_x(gx[j], gy[j], nx, ny, px, py, dx, u[j], DX[j]);
-        diff_y(gx[j], gy[j], nx, ny, px, py, dy, u[j], DY[j]);
+        DX[j] = (double*)malloc(sizeof(double) * (size_t)npts(3 - gx[j], nx, px) * (size_t)npts(gy[j], ny, py));
+        DY[j] = (double*)malloc(sizeof(double) * (size_t)npts(gx[j], nx, px) * (size_t)npts(3 - gy[j], ny, py));
     }
-    for (int k = 0; k < nmom && status == 0; ++k) {
-        int even_k = gx[k] == gy[k];
-        if ((parity == 0) != even_k) continue;
-        size_t sz = plane_size(gx, gy, k, nx, ny, px, py);
-        double* w = W[k];
-        for (size_t t = 0; t < sz; ++t) w[t] = 0.0;
+#pragma omp parallel
+    {
         for (int j = 0; j < nmom; ++j) {
-            double mx = Mx[(size_t)k * nmom + j];
-            double my = My[(size_t)k * nmom + j];
-            if (mx != 0.0) {
-                if (!DX[j] || 3 - gx[j] != gx[k] || gy[j] != gy[k]) { status = -1; break; }
-                const double* d = DX[j];
-#pragma omp parallel for schedule(static)
-                for (long long t = 0; t < (long long)sz; ++t) w[t] -= mx * d[t];
-            }
-            if (my != 0.0) {
-                if (!DY[j] || gx[j] != gx[k] || 3 - gy[j] != gy[k]) { status = -1; break; }
-                const double* d = DY[j];
-#pragma omp parallel for schedule(static)
-                for (long long t = 0; t < (long long)sz; ++t) w[t] -= my * d[t];
+            if (!DX[j]) continue;
+            const int cols = npts(gx[j], nx, px), rows = npts(gy[j], ny, py);
+            const int ndx = npts(3 - gx[j], nx, px), ndy = npts(3 - gy[j], ny, py);
+#pragma omp for schedule(static) nowait
+            for (int r = 0; r < rows; ++r)
+                diff_x_row(gx[j], nx, px, dx, u[j] + (size_t)r * cols, DX[j] + (size_t)r * ndx);
+#pragma omp for schedule(static)
+            for (int a = 0; a < ndy; ++a)
+                diff_y_row(gy[j], ny, py, dy, cols, u[j], a, DY[j] + (size_t)a * cols);
+        }
+        for (int k = 0; k < nmom; ++k) {
+            int even_k = gx[k] == gy[k];
+            if ((parity == 0) != even_k) continue;
+            const int cols = npts(gx[k], nx, px), rows = npts(gy[k], ny, py);
+#pragma omp for schedule(static) nowait
+            for (int r = 0; r < rows; ++r) {
+                double* w = W[k] + (size_t)r * cols;
+                for (int i = 0; i < cols; ++i) w[i] = 0.0;
+                for (int j = 0; j < nmom; ++j) {
+                    const double mx = Mx[(size_t)k * nmom + j];
+                    const double my = My[(size_t)k * nmom + j];
+                    if (mx != 0.0) {
+                        const double* d = DX[j] + (size_t)r * cols;
+                        for (int i = 0; i < cols; ++i) w[i] -= mx * d[i];
+                    }
+                    if (my != 0.0) {
+                        const double* d = DY[j] + (size_t)r * cols;
+                        for (int i = 0; i < cols; ++i) w[i] -= my * d[i];
+                    }
+                }
             }
         }
     }
     for (int j = 0; j < nmom; ++j) { free(DX[j]); free(DY[j]); }
     free(DX);
     free(DY);
-    return status;
+    return 0;
 }
 
 /*
@@ -181,6 +175,7 @@ int starmap_oracle_flux(int nx, int ny, int px, int py, double dx, double dy, in
 int starmap_oracle_update(int nx, int ny, int px, int py, int nmom, const int* gx, const int* gy,
                           int parity, double* const* u, double* const* W,
                           double* const* c, double* const* q, double tau, int emode) {
+#pragma omp parallel
     for (int k = 0; k < nmom; ++k) {
         int even_k = gx[k] == gy[k];
         if ((parity == 0) != even_k) continue;
@@ -189,7 +184,7 @@ int starmap_oracle_update(int nx, int ny, int px, int py, int nmom, const int* g
         const double* wk = W[k];
         const double* ck = c[k];
         const double* qk = q ? q[k] : NULL;
-#pragma omp parallel for schedule(static)
+#pragma omp for schedule(static) nowait
         for (long long t = 0; t < (long long)sz; ++t) {
             double r = wk[t] + (qk ? qk[t] : 0.0);
             double cc = ck[t];

@@ -90,6 +90,8 @@ SIGNATURES = [
     ("starmap_set_variant", [_vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_get_variant", [_vp, _i32p, _i32p, _i32p], ctypes.c_int),
     ("starmap_autotune", [_vp, ctypes.c_int32], ctypes.c_int),
+    ("starmap_set_range_width", [_vp, ctypes.c_int32], ctypes.c_int),
+    ("starmap_get_range_width", [_vp, _i32p], ctypes.c_int),
     ("starmap_sweep_bytes", [_vp, ctypes.c_int32, _dp], ctypes.c_int),
     ("starmap_profile_begin", [_vp], ctypes.c_int),
     ("starmap_profile_end", [_vp, _dp, _i64p, _dp], ctypes.c_int),

@@ -976,7 +976,11 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out) {
   s->pitch = int((s->nx + 1 + 63) / 64 * 64);
   s->nrows = s->ny + 1;
   s->plane_stride = (int64_t(s->pitch) * s->nrows + 127) / 128 * 128;
-  if (s->plane_stride >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "grid too large for 32-bit plane offsets");
+  // The kernels address a plane with 32-bit byte offsets (element offset
+  // times the storage or compute size, whichever is larger): keep every such
+  // offset below 2^31.
+  if (s->plane_stride * int64_t(std::max(s->ssize, s->csize)) >= (int64_t(1) << 31))
+    return fail(STARMAP_EINVAL, "grid too large for 32-bit plane byte offsets");
   layout(s.get());
   *out = s.release();
   return STARMAP_OK;
@@ -1431,6 +1435,30 @@ int starmap_set_variant(starmap_solver* s, int32_t v) {
     }
     return upload_program(s);
   }
+  return STARMAP_OK;
+}
+
+int starmap_set_range_width(starmap_solver* s, int32_t width) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (std::find(std::begin(kChunkWidths), std::end(kChunkWidths), width) == std::end(kChunkWidths))
+    return fail(STARMAP_EINVAL, "unsupported m-range width");
+  const int keep = s->chunk_width;
+  s->chunk_width = width;
+  s->nchunks = sweep_chunk_count(s->N, width);
+  if (!s->device_ready) return STARMAP_OK;
+  int rc = upload_program(s);
+  if (!rc && sweep_lds_bytes(s->variant, s->slots, s->storage) > size_t(max_lds_bytes()))
+    rc = fail(STARMAP_EINVAL, "the tile variant does not fit the LDS at this m-range width");
+  if (rc) {
+    s->chunk_width = keep;
+    (void)upload_program(s);
+  }
+  return rc;
+}
+
+int starmap_get_range_width(const starmap_solver* s, int32_t* width) {
+  if (!s || !width) return fail(STARMAP_EINVAL, "bad arguments");
+  *width = s->chunk_width;
   return STARMAP_OK;
 }
 

@@ -1,5 +1,5 @@
 // Decay and source planes of time-separable data, formed on the device once
-// per step (time-dependent data are frozen at t + dt/2 for a step, Sect. 5.6):
+// per step (time-dependent data are frozen at t + dt/2 for a step, Sect. 5.7):
 // each output plane is a short linear combination of basis planes g_i whose
 // time factors a_i(t + dt/2) arrive as kernel arguments.  HBM-bound: per
 // output point one read per entry and one write.

@@ -10,7 +10,7 @@
 //   inputs  : 3 x 3 array stencils of the eleven order-4/5 moments divided by
 //             their norm nu, log10(sigma_a + 0.01), log10(sigma_s + 0.01),
 //             zero padding to 128;
-//   network : 128 -> 128 -> 128 -> 6, exact-erf GELU after the hidden layers;
+//   network : 128 -> 128 -> 128 -> 6, GELU after the hidden layers;
 //   output  : g = nu * y / dx added to the residual of the six order-5 moments.
 // Matrix-product operands are rounded to bfloat16 (nearest, ties to even);
 // accumulation, biases and activations before rounding are FP32.
@@ -47,9 +47,22 @@ __device__ __forceinline__ uint32_t bf16_hw(float v) {
 __device__ __forceinline__ uint32_t bf16_in(float v) { return bf16_hw(v); }
 __device__ __forceinline__ uint32_t bf16_in(double v) { return bf16_bits(v); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU z Phi(z), Phi the standard normal distribution function, with erf
+// from Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26
+// (|error| <= 1.5e-7 on the real line).  Training and inference use this one
+// definition.
+__device__ __forceinline__ float normal_cdf(float z) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  const float erf_abs = 1.0f - poly * __expf(-x * x);
+  return 0.5f * (1.0f + copysignf(erf_abs, z));
+}
+__device__ __forceinline__ float gelu(float z) { return z * normal_cdf(z); }
+// d/dz z Phi(z) = Phi(z) + z phi(z)
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  return normal_cdf(z) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
@@ -314,17 +327,6 @@ __global__ void __launch_bounds__(256) closure_samples_kernel(const T* __restric
 constexpr int CB = 64;               // evaluation points per block
 constexpr int LDW = CLOSURE_IN + 8;  // LDS row of one point's activations (bf16), padded
 
-// GELU with erf from Abramowitz & Stegun, Handbook of Mathematical Functions,
-// formula 7.1.26 (|error| <= 1.5e-7 on the real line).
-__device__ __forceinline__ float gelu_fast(float z) {
-  const float x = fabsf(z) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-  const float poly =
-      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
-  const float erf_abs = 1.0f - poly * __expf(-x * x);
-  return 0.5f * z * (1.0f + copysignf(erf_abs, z));
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U,
                                                             const typename ComputeOf<T>::type* __restrict__ decay,
@@ -478,10 +480,10 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
           const float4 bv = *reinterpret_cast<const float4*>((layer == 0 ? net->b1 : net->b2) + 32 * w + 16 * mi +
                                                              4 * (lane >> 4));
           uint32_t h[4];
-          h[0] = bf16_hw(gelu_fast(acc[mi][nj][0] + bv.x));
-          h[1] = bf16_hw(gelu_fast(acc[mi][nj][1] + bv.y));
-          h[2] = bf16_hw(gelu_fast(acc[mi][nj][2] + bv.z));
-          h[3] = bf16_hw(gelu_fast(acc[mi][nj][3] + bv.w));
+          h[0] = bf16_hw(gelu(acc[mi][nj][0] + bv.x));
+          h[1] = bf16_hw(gelu(acc[mi][nj][1] + bv.y));
+          h[2] = bf16_hw(gelu(acc[mi][nj][2] + bv.z));
+          h[3] = bf16_hw(gelu(acc[mi][nj][3] + bv.w));
           const int m = 16 * nj + (lane & 15);
           const int n = 32 * w + 16 * mi + 4 * (lane >> 4);
           *reinterpret_cast<uint2*>(&Xout[m * LDW + n]) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));

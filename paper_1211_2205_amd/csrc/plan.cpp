@@ -216,7 +216,7 @@ double spectral_radius_x(const std::vector<CouplingRow>& rows) {
 void time_step(double cfl, double dx, double dy, double rho, double t_final, double* dt,
                int64_t* nsteps) {
   // Thm. 1 (dt < h for P_1), scaled by 1/rho(M) and by the 2D factor carried in
-  // cfl (Sect. 4.6); the step count is rounded up so the run lands on t_final.
+  // cfl (Sect. 4.5); the step count is rounded up so the run lands on t_final.
   double dt0 = cfl * std::min(dx, dy) / rho;
   int64_t n = (int64_t)std::ceil(t_final / dt0 - 1e-12);
   if (n < 1) n = 1;

@@ -352,6 +352,15 @@ class Solver:
     def autotune(self, sweeps=3):
         B.check(B.lib().starmap_autotune(self._h, int(sweeps)))
 
+    def set_chunk_width(self, width):
+        """m-range width of the sweep (4, 6 or 8)."""
+        B.check(B.lib().starmap_set_range_width(self._h, int(width)))
+
+    def chunk_width(self):
+        w = ctypes.c_int32()
+        B.check(B.lib().starmap_get_range_width(self._h, ctypes.byref(w)))
+        return w.value
+
     def profile_begin(self):
         B.check(B.lib().starmap_profile_begin(self._h))
 

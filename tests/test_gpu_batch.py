@@ -9,7 +9,7 @@ import pytest
 
 import paper_1211_2205_amd as pa
 import workloads as wl
-from gpu_helpers import rel_l2, run_oracle
+from gpu_helpers import assert_parity, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -65,8 +65,7 @@ def test_batch_equals_single_runs_and_oracle(monkeypatch):
         print("single", p.name, flush=True)
         assert _identical(g, _single(p, 0, 8, monkeypatch)), p.name
         o = run_oracle(p, fused=False)
-        err = rel_l2(g, o.u)
-        assert err < 1e-12, (p.name, err)
+        assert_parity(g, o.u, 1e-12, p.name)
     b.close()
 
 
@@ -114,8 +113,7 @@ def test_batch_fp32_and_autotune(monkeypatch):
     for p, s in zip(probs, solvers):
         g = s.moments()
         assert _identical(g, _single(p, v, w, monkeypatch)), p.name
-        err = rel_l2(g, run_oracle(p).u)
-        assert err < 1e-5, (p.name, err)
+        assert_parity(g, run_oracle(p).u, 1e-5, p.name)
     b.close()
 
 
@@ -151,8 +149,7 @@ def test_c4_full_batch_sampled_instances(monkeypatch):
     for i in pick:
         assert _identical(solvers[i].moments(), _single(probs[i], 0, 8, monkeypatch)), probs[i].name
     i = int(np.argmin(sizes))
-    err = rel_l2(solvers[i].moments(), run_oracle(probs[i]).u)
-    assert err < 1e-5, (probs[i].name, err)
+    assert_parity(solvers[i].moments(), run_oracle(probs[i]).u, 1e-5, probs[i].name)
     for s in solvers:
         d = s.diagnostics()
         assert d["nonfinite"] == 0 and d["maxabs"] > 0
@@ -173,5 +170,5 @@ def test_batch_of_filtered_and_anisotropic_instances(monkeypatch):
     b.run()
     for p, s in zip(probs, solvers):
         assert _identical(s.moments(), _single(p, 6, 6, monkeypatch)), p.name
-        assert rel_l2(s.moments(), run_oracle(p).u) < 1e-12, p.name
+        assert_parity(s.moments(), run_oracle(p).u, 1e-12, p.name)
     b.close()

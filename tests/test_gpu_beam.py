@@ -8,7 +8,7 @@ import pytest
 
 import paper_1211_2205_amd as pa
 import workloads as wl
-from gpu_helpers import rel_l2, run_gpu, run_oracle
+from gpu_helpers import assert_parity, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -17,9 +17,7 @@ def test_beam_p9_150_matches_oracle():
     prob = wl.beam(N=9, n=150, t_final=0.6)
     s, g = run_gpu(prob)
     o = run_oracle(prob)
-    err = rel_l2(g, o.u)
-    print(f"beam P9 150^2 FP64 {s.nsteps} steps: rel L2 {err:.3e}", flush=True)
-    assert err < 1e-12
+    assert_parity(g, o.u, 1e-12, f"beam P9 150^2 FP64 {s.nsteps} steps:")
 
 
 def test_beam_p39_small_matches_oracle():
@@ -27,9 +25,7 @@ def test_beam_p39_small_matches_oracle():
     prob = wl.beam(N=39, n=60, t_final=0.2)
     s, g = run_gpu(prob, nsteps=20)
     o = run_oracle(prob, nsteps=20)
-    err = rel_l2(g, o.u)
-    print(f"beam P39 60^2 FP64 20 steps: rel L2 {err:.3e}", flush=True)
-    assert err < 1e-12
+    assert_parity(g, o.u, 1e-12, "beam P39 60^2 FP64 20 steps:")
 
 
 def test_beam_p39_150_fp32_mass_and_direction():

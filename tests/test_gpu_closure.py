@@ -7,7 +7,7 @@ import torch
 
 import paper_1211_2205_amd as pa
 import workloads as wl
-from gpu_helpers import rel_l2
+from gpu_helpers import assert_parity, rel_l2
 from oracle import closure as oc
 from oracle import mlp
 from oracle.scheme import OracleSolver
@@ -162,9 +162,7 @@ def test_closure_solver_matches_oracle(n, bc):
     s.synchronize()
     o.advance(steps)
     got = s.moments()
-    err = rel_l2(got, o.u)
-    print("closure solver fp64 rel L2", err, flush=True)
-    assert err < 1e-5
+    err = assert_parity(got, o.u, 1e-5, "closure solver fp64:")[0]
     # the closure changes the answer: plain P_5 differs by far more
     plain = OracleSolver(prob)
     plain.advance(steps, fused=True)
@@ -178,9 +176,7 @@ def test_closure_solver_fp32_matches_oracle():
     s.advance(10)
     s.synchronize()
     o.advance(10)
-    err = rel_l2(s.moments(), o.u)
-    print("closure solver fp32 rel L2", err, flush=True)
-    assert err < 1e-5
+    assert_parity(s.moments(), o.u, 1e-5, "closure solver fp32:")
 
 
 def test_zero_output_layer_equals_plain_p5():

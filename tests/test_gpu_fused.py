@@ -8,7 +8,7 @@ import pytest
 
 import paper_1211_2205_amd as pa
 import workloads as wl
-from gpu_helpers import rel_l2, run_oracle
+from gpu_helpers import assert_parity, rel_l2, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,7 @@ def test_fused_equals_separate_sweeps_bitwise(name, make, n, bc, precision):
     _say(f"{name} {precision} {n} {bc}: identical {_identical(a, b)}, rel L2 {rel_l2(b, a):.3e}")
     assert _identical(a, b)
     if precision == "fp64":
-        assert rel_l2(b, run_oracle(prob).u) < 1e-12
+        assert_parity(b, run_oracle(prob).u, 1e-12, f"{name} fused vs oracle:")
 
 
 def test_fused_bf16_filtered_anisotropic():
@@ -70,7 +70,7 @@ def test_fused_bf16_filtered_anisotropic():
     a = _run(beam, False)
     b = _run(beam, True)
     assert _identical(a, b)
-    assert rel_l2(b, run_oracle(beam).u) < 1e-12
+    assert_parity(b, run_oracle(beam).u, 1e-12, "fused filtered beam vs oracle:")
     prob = wl.random_medium(54, 4, 48, t_final=0.2, precision="bf16")
     a = _run(prob, False, "bf16")
     b = _run(prob, True, "bf16")

@@ -9,7 +9,7 @@ import pytest
 
 import paper_1211_2205_amd as pa
 import workloads as wl
-from gpu_helpers import rel_l2, run_oracle
+from gpu_helpers import assert_parity, rel_l2, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -44,9 +44,7 @@ def test_fpn_fp64_matches_oracle(N):
     prob = _fpn_checker(N)
     s, g = _run(prob, splits=[2])
     o = run_oracle(prob)
-    err = rel_l2(g, o.u)
-    _say(f"FP_N checkerboard P{N} 70^2: rel L2 {err:.3e}")
-    assert err < FP64_TOL
+    err = assert_parity(g, o.u, FP64_TOL, f"FP_N checkerboard P{N} 70^2:")[0]
     # the damping matters
     plain = _fpn_checker(N)
     plain.filter_damping = None
@@ -56,15 +54,11 @@ def test_fpn_fp64_matches_oracle(N):
 def test_fpn_fp32_and_anisotropic_beam():
     prob = _fpn_checker(7, precision="fp32")
     _, g = _run(prob, precision="fp32")
-    err = rel_l2(g, run_oracle(prob).u)
-    _say(f"FP_N checkerboard P7 fp32: rel L2 {err:.3e}")
-    assert err < FP32_TOL
+    assert_parity(g, run_oracle(prob).u, FP32_TOL, "FP_N checkerboard P7 fp32:")
     beam = wl.beam(N=9, n=60, t_final=0.3)
     beam.filter_damping = wl.filter_damping(9, 20.0, power=2)
     _, g = _run(beam)
-    err = rel_l2(g, run_oracle(beam).u)
-    _say(f"FP_N beam P9 60^2 (anisotropic scattering): rel L2 {err:.3e}")
-    assert err < FP64_TOL
+    assert_parity(g, run_oracle(beam).u, FP64_TOL, "FP_N beam P9 60^2 (anisotropic scattering):")
 
 
 def test_fpn_with_separable_data_and_a_later_change():
@@ -84,9 +78,7 @@ def test_fpn_with_separable_data_and_a_later_change():
     o.advance(5)
     o.prob.filter_damping = d2
     o.advance(o.nsteps - 5)
-    err = rel_l2(s.moments(), o.u)
-    _say(f"FP_N manufactured, damping changed after 5 steps: rel L2 {err:.3e}")
-    assert err < FP64_TOL
+    assert_parity(s.moments(), o.u, FP64_TOL, "FP_N manufactured, damping changed after 5 steps:")
 
 
 def _dn_problem(N, n, bc, precision="fp64"):
@@ -104,9 +96,7 @@ def test_dn_fp64_matches_oracle(N, bc):
     prob = _dn_problem(N, 61, bc)
     s, g = _run(prob, splits=[1, 3])
     o = run_oracle(prob)
-    err = rel_l2(g, o.u)
-    _say(f"D_N line source P{N} 61^2 {bc}: {s.nsteps} steps, rel L2 {err:.3e}")
-    assert err < FP64_TOL
+    err = assert_parity(g, o.u, FP64_TOL, f"D_N line source P{N} 61^2 {bc}: {s.nsteps} steps,")[0]
     plain = _dn_problem(N, 61, bc)
     plain.diffusion = None
     assert rel_l2(run_oracle(plain).u, o.u) > 1e4 * max(err, 1e-17)
@@ -115,15 +105,11 @@ def test_dn_fp64_matches_oracle(N, bc):
 def test_dn_fp32_and_separable():
     prob = _dn_problem(7, 64, (wl.BC_EXTRAPOLATION, wl.BC_EXTRAPOLATION), precision="fp32")
     _, g = _run(prob, precision="fp32")
-    err = rel_l2(g, run_oracle(prob).u)
-    _say(f"D_N line source P7 fp32: rel L2 {err:.3e}")
-    assert err < FP32_TOL
+    assert_parity(g, run_oracle(prob).u, FP32_TOL, "D_N line source P7 fp32:")
     man = wl.manufactured(40)
     man.diffusion = lambda t, x, y: 1e-4 + 0 * x
     _, g = _run(man)
-    err = rel_l2(g, run_oracle(man).u)
-    _say(f"D_N manufactured (separable data): rel L2 {err:.3e}")
-    assert err < FP64_TOL
+    assert_parity(g, run_oracle(man).u, FP64_TOL, "D_N manufactured (separable data):")
 
 
 def test_dn_errors():

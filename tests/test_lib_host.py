@@ -216,3 +216,32 @@ def test_fused_mode_is_validated_on_the_host():
         pa.Solver(pa._binding.FUSED_MAX_ORDER + 1, (20, 20), (0, 1, 0, 1)).set_fused(True)
     with pytest.raises(pa.StarmapError):
         pa.Solver(5, (20, 20), (0, 1, 0, 1), closure="learned").set_fused(True)
+
+
+@pytest.mark.parametrize("precision,n_ok,n_bad", [("fp64", 16000, 16400), ("fp32", 23000, 23200),
+                                                  ("bf16", 23000, 23200)])
+def test_create_rejects_planes_beyond_32bit_byte_offsets(precision, n_ok, n_bad):
+    """The kernels address a plane with 32-bit byte offsets (element offset
+    times the larger of the storage and compute sizes): starmap_create must
+    reject a grid whose plane reaches 2^31 bytes and accept one just below.
+    Host only: no such grid is ever launched."""
+    def create(n):
+        prob = wl.line_source(N=1, n=n, s=0.1, precision=precision)
+        return pa.Solver.from_problem(prob)
+    s = create(n_ok)
+    s.close()
+    with pytest.raises(pa.StarmapError) as e:
+        create(n_bad)
+    assert e.value.code == -1 and "32-bit" in str(e.value)
+
+
+def test_range_width_setter():
+    s = pa.Solver.from_problem(wl.config("c2"))
+    assert s.chunk_width() == 8
+    for w in (4, 6, 8):
+        s.set_chunk_width(w)
+        assert s.chunk_width() == w
+    for bad in (0, 5, 12):
+        with pytest.raises(pa.StarmapError):
+            s.set_chunk_width(bad)
+    assert s.chunk_width() == 8

@@ -45,7 +45,7 @@ def test_transformation_unitary_and_matrices_real_symmetric(N):
     assert Mx.shape == ((N + 1) * (N + 2) // 2,) * 2
     np.testing.assert_allclose(Mx, Mx.T, atol=1e-15)  # symmetric (eq. real_valued_pn_equations)
     np.testing.assert_allclose(My, My.T, atol=1e-15)
-    # at most four nonzeros per row of each matrix (Sect. 5.4)
+    # at most four nonzeros per row of each matrix (Sect. 5.5)
     assert np.max(np.count_nonzero(Mx, axis=1)) <= 4
     assert np.max(np.count_nonzero(My, axis=1)) <= 4
 

@@ -32,7 +32,7 @@ def test_expm1div():
     for z in (-50.0, -3.0, -1e-3, -2e-4, -1e-9, 0.0, 1e-9, 2e-4, 1e-3, 2.0):
         ref = 1.0 if z == 0 else math.expm1(z) / z
         assert abs(expm1div(z, 0) - ref) <= 2e-16 * abs(ref)
-    # the paper's switched evaluation stays below 1e-12 total error (Sect. 5.5)
+    # the paper's switched evaluation stays below 1e-12 total error (Sect. 5.6)
     for z in np.concatenate([np.linspace(-3e-4, 3e-4, 601), -np.logspace(-12, -1, 50)]):
         ref = 1.0 if z == 0 else math.expm1(z) / z
         assert abs(expm1div(float(z), 1) - ref) < 1e-12
@@ -109,7 +109,7 @@ def _growth(Mx, My, gx, gy, c, kx, ky, dx, dy, dt):
     """Amplification matrix of one full step for the mode exp(i(kx x + ky y)),
     built from the half-step operators: a_k <- exp(-c_k tau) a_k
     + tau E(-c_k tau) sum_j A_kj a_j with A = -(M_x sx + M_y sy),
-    sx = (2i/dx) sin(kx dx / 2) (Sect. 4.6), G = G^o G^e G^e G^o."""
+    sx = (2i/dx) sin(kx dx / 2) (Sect. 4.5), G = G^o G^e G^e G^o."""
     n = len(c)
     sx = 2j / dx * math.sin(kx * dx / 2)
     sy = 2j / dy * math.sin(ky * dy / 2)
@@ -426,3 +426,37 @@ def test_zero_diffusion_is_plain_pn():
     b.run()
     for x, y in zip(a.u, b.u):
         assert np.array_equal(x, y)
+
+
+# ------------------------------------------------ extrapolation ghost rule
+def test_extrapolation_ghosts_on_linear_fields():
+    """Constant extrapolation onto ghost points (Sect. 4.2), pinned on linear
+    fields by hand-computed differences.  P_1 on 6 x 5 cells of width h = 0.5,
+    extrapolation on both axes, R_0^0 = 2 x + 3 y on G11 (cell centres):
+      * D_x R_0^0 on the nodes 0..6 of G21: ghost cell 0 := cell 1 and ghost
+        cell 7 := cell 6, so the difference is 0 at nodes 0 and 6 and exactly 2
+        at the five inner nodes;
+      * D_y R_0^0 on the nodes 0..5 of G12: 0 at nodes 0 and 5, exactly 3 inside.
+    The odd residuals are W = -Mx(R_1^1, R_0^0) D_x R_0^0 and
+    W = -My(I_1^1, R_0^0) D_y R_0^0 (their only couplings; the entries are the
+    printed P_1 block, pinned in test_oracle_matrices).  A ghost taken one cell
+    too far in (ghost := cell 2) would give -2 and -3 at the boundary nodes,
+    an unassigned ghost (0) would give the boundary value itself.  Nodal
+    fields need no ghost with extrapolation: R_1^1 = 5 x on G21 gives
+    D_x = 5 in every cell, boundary cells included."""
+    h = 0.5
+    prob = _problem(1, (6, 5), (0, 6 * h, 0, 5 * h), EXT, 0.0, 0.0,
+                    initial={0: lambda t, x, y: 2.0 * x + 3.0 * y,
+                             1: lambda t, x, y: 5.0 * x + 0.0 * y})
+    o = OracleSolver(prob)
+    mx, my = float(o.Mx[1, 0]), float(o.My[2, 0])
+    assert abs(mx - 1.0 / math.sqrt(3.0)) < 1e-15 and abs(abs(my) - 1.0 / math.sqrt(3.0)) < 1e-15
+    W = o.flux(1)
+    dx_expect = np.array([0.0, 2.0, 2.0, 2.0, 2.0, 2.0, 0.0])           # nodes 0..6
+    dy_expect = np.array([0.0, 3.0, 3.0, 3.0, 3.0, 0.0])                # nodes 0..5
+    assert W[1].shape == (5, 7) and W[2].shape == (6, 6)
+    np.testing.assert_allclose(W[1], -mx * np.broadcast_to(dx_expect, (5, 7)), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(W[2], -my * np.broadcast_to(dy_expect[:, None], (6, 6)), rtol=0, atol=1e-13)
+    # even residual from the nodal R_1^1 = 5 x (I_1^1 = 0): D_x = 5 on all 6 cells
+    W0 = o.flux(0)
+    np.testing.assert_allclose(W0[0], np.full((5, 6), -mx * 5.0), rtol=0, atol=1e-13)

@@ -322,7 +322,7 @@ def config(name: str, precision: Optional[str] = None) -> Problem:
     if name == "c2":
         return checkerboard(N=7, n=280, precision=precision or "fp64")
     if name == "c3":
-        return line_source(N=39, n=1000, s=0.01, precision=precision or "fp32")
+        return line_source(N=39, n=1000, s=0.01, precision=precision or "fp64")
     raise KeyError(name)
 
 
