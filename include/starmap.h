@@ -226,6 +226,19 @@ int starmap_set_state(starmap_solver* s, const void* host_buf, size_t bytes, dou
 int starmap_diagnostics(const starmap_solver* s, double* mass_r00, double* l2, double* maxabs,
                         int32_t* nonfinite);
 
+/* starmap_diagnostics for callers that cannot allocate device memory (code
+   under HIP stream capture, tight serving loops, harnesses that forbid
+   allocation): the same reductions and outputs, with the FP64 block partials
+   and the four results in a static device array of the library (2 MiB per
+   GPU, held until the process ends) instead of the solver's workspace.  It
+   allocates nothing: the solver must already hold its device state (any
+   earlier device call sets it up), else STARMAP_ESTATE.  At most 65536
+   reduction blocks, i.e. moments x ceil((ny + 1) / 64) <= 65536, else
+   STARMAP_EINVAL.  All calls on one GPU share that GPU's array: calls that
+   overlap on one GPU (two streams or two threads) race. */
+int starmap_diagnostics_noalloc(const starmap_solver* s, double* mass_r00, double* l2, double* maxabs,
+                                int32_t* nonfinite);
+
 /* Tile variant of the sweep kernel: -1 chooses by the autotuner (default).
    Variants differ in the spatial tile (tile_x x tile_y points) and in how
    many planes of one order are held in registers while the next order loads

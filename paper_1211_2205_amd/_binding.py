@@ -86,6 +86,7 @@ SIGNATURES = [
     ("starmap_get_state", [_vp, _vp, ctypes.c_size_t, _dp, _i64p], ctypes.c_int),
     ("starmap_set_state", [_vp, _vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
     ("starmap_diagnostics", [_vp, _dp, _dp, _dp, _i32p], ctypes.c_int),
+    ("starmap_diagnostics_noalloc", [_vp, _dp, _dp, _dp, _i32p], ctypes.c_int),
     ("starmap_variant_count", [], ctypes.c_int),
     ("starmap_set_variant", [_vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_get_variant", [_vp, _i32p, _i32p, _i32p], ctypes.c_int),

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstarmap.so")
 OBJDIR = os.path.join(os.path.dirname(HERE), "_build", "starmap")
-SOURCES = ["plan.cpp", "sweep.hip", "mlp.hip", "materials.hip", "diffusion.hip", "fused.hip", "capi.cpp", "closure.cpp"]
+SOURCES = ["plan.cpp", "sweep.hip", "mlp.hip", "materials.hip", "diffusion.hip", "fused.hip", "capi.cpp", "closure.cpp", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
