@@ -197,6 +197,15 @@ int starmap_bind_device(starmap_solver* s, void* dev_ptr, size_t bytes, void* hi
    The call returns after queueing the work on the stream (asynchronous). */
 int starmap_advance(starmap_solver* s, int64_t nsteps);
 
+/* HIP graphs in starmap_advance (on by default): for time-independent data
+   (and not with starmap_set_fused), the repeated pairs S^e_dt, S^o_dt are
+   captured once per run length of 16, 8, 4, 2 and 1 pairs and replayed as
+   graph launches; the captured launches are those of the eager path, so the
+   results are the same bits.  Not used while per-launch timing is on
+   (starmap_profile_begin) or on the null stream.  The graphs are dropped
+   when the tile variant or m-range width changes, and with enable = 0. */
+int starmap_set_graphs(starmap_solver* s, int32_t enable);
+
 /* Advance to t_final and synchronise. */
 int starmap_run(starmap_solver* s);
 
@@ -309,6 +318,19 @@ int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches,
    precede the first advance of a closure solver. */
 int starmap_closure_load(starmap_solver* s, const float* weights, size_t count);
 
+/* How the closure enters the odd sweep.  enable = 1 (default): one kernel
+   evaluates the network on blocks of 64 evaluation points and applies the
+   odd sub-step of P_5 to those points in the same workgroup; the order-5
+   moments are read from one buffer and written to a second one (the state
+   planes and the closure planes take turns; every call leaves them in the
+   state planes), so every stencil sees the state at the start of the sweep.
+   enable = 0: a network kernel writes the closure terms to the closure planes
+   and the odd sweep kernel reads them like sources.  Both give the same
+   bits for FP64 and FP32 storage (with BF16 storage, 0 rounds the closure
+   terms to bfloat16 on the way through the closure planes).
+   STARMAP_ESTATE if the solver is not a closure solver. */
+int starmap_closure_set_fused(starmap_solver* s, int32_t enable);
+
 /* Training samples from the current state of a solver of order N >= 6
    (isotropic scattering): for count cells points[2 i], points[2 i + 1] =
    (i, j) with 0 <= i < nx, 0 <= j < ny, writes the closure inputs
@@ -319,6 +341,14 @@ int starmap_closure_load(starmap_solver* s, const float* weights, size_t count);
    arrays are caller-owned device memory; the call synchronises. */
 int starmap_closure_samples(starmap_solver* s, const int32_t* points, int32_t count, float* features,
                             float* targets);
+
+/* Closure inputs alone, from the current state of a solver of order N >= 5
+   (a P_5 solver included): features as in starmap_closure_samples, and, if nu
+   is not NULL, the stencil norm nu of each sample (count values, FP32).  A
+   training set for states the closure solver itself produces pairs these
+   inputs with the flux of a high-order run at the same time and cells,
+   rescaled to this nu.  Device arrays, caller-owned; synchronises. */
+int starmap_closure_features(starmap_solver* s, const int32_t* points, int32_t count, float* features, float* nu);
 
 /* Network trainer on the device: parameters (FP32 master copy), Adam state,
    and buffers for batches of up to max_batch samples; work runs on

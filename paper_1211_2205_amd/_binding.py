@@ -86,18 +86,21 @@ SIGNATURES = [
     ("starmap_get_state", [_vp, _vp, ctypes.c_size_t, _dp, _i64p], ctypes.c_int),
     ("starmap_set_state", [_vp, _vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
     ("starmap_diagnostics", [_vp, _dp, _dp, _dp, _i32p], ctypes.c_int),
-    ("starmap_diagnostics_noalloc", [_vp, _dp, _dp, _dp, _i32p], ctypes.c_int),
     ("starmap_variant_count", [], ctypes.c_int),
     ("starmap_set_variant", [_vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_get_variant", [_vp, _i32p, _i32p, _i32p], ctypes.c_int),
     ("starmap_autotune", [_vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_set_range_width", [_vp, ctypes.c_int32], ctypes.c_int),
+    ("starmap_set_graphs", [_vp, ctypes.c_int32], ctypes.c_int),
+    ("starmap_closure_set_fused", [_vp, ctypes.c_int32], ctypes.c_int),
+    ("starmap_diagnostics_noalloc", [_vp, _dp, _dp, _dp, _i32p], ctypes.c_int),
     ("starmap_get_range_width", [_vp, _i32p], ctypes.c_int),
     ("starmap_sweep_bytes", [_vp, ctypes.c_int32, _dp], ctypes.c_int),
     ("starmap_profile_begin", [_vp], ctypes.c_int),
     ("starmap_profile_end", [_vp, _dp, _i64p, _dp], ctypes.c_int),
     ("starmap_closure_load", [_vp, _fp, ctypes.c_size_t], ctypes.c_int),
     ("starmap_closure_samples", [_vp, _i32p, ctypes.c_int32, _vp, _vp], ctypes.c_int),
+    ("starmap_closure_features", [_vp, _i32p, ctypes.c_int32, _vp, _vp], ctypes.c_int),
     ("starmap_mlp_create", [ctypes.c_int32, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
     ("starmap_mlp_destroy", [_vp], None),
     ("starmap_mlp_set_params", [_vp, _fp, ctypes.c_size_t], ctypes.c_int),

@@ -420,6 +420,9 @@ void layout(starmap_solver* s) {
   if (s->closure) {
     s->off_net = off;
     off += align256(sizeof(ClosureNet));
+    // the even sweep's program reading the order-5 moments from the closure planes
+    s->off_prog_b = off;
+    off += s->prog_bytes[0];
   }
   plan_separable(s);
   if (s->separable) {
@@ -447,14 +450,10 @@ void layout(starmap_solver* s) {
   s->dev_bytes = off;
 }
 
-int upload_program(starmap_solver* s) {
-  const TileShape ts = sweep_variant(s->variant);
-  s->nchunks = sweep_chunk_count(s->N, s->chunk_width);
-  for (int p = 0; p < 2; ++p) {
-    s->prog[p] = build_sweep_program(s->N, p, ts.tx, ts.ty, s->dx, s->dy, s->rows, s->dmap, s->qk, s->nchunks);
-    const auto& pr = s->prog[p];
-    if (program_bytes(pr, s->csize) > s->prog_bytes[p]) return fail(STARMAP_ENOMEM, "sweep program region too small");
-    std::vector<char> buf(s->prog_bytes[p], 0);
+int upload_one_program(starmap_solver* s, const SweepProgram& pr, size_t region, size_t region_bytes) {
+  if (program_bytes(pr, s->csize) > region_bytes) return fail(STARMAP_ENOMEM, "sweep program region too small");
+  {
+    std::vector<char> buf(region_bytes, 0);
     size_t o = 0;
     {
       std::vector<int32_t> ch;
@@ -481,8 +480,37 @@ int upload_program(starmap_solver* s) {
       std::vector<float> cf(pr.coefs.begin(), pr.coefs.end());
       std::memcpy(buf.data() + o, cf.data(), cf.size() * 4);
     }
-    HIP_TRY(hipMemcpyAsync(dptr(s, s->off_prog[p]), buf.data(), buf.size(), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(dptr(s, region), buf.data(), buf.size(), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return STARMAP_OK;
+}
+
+int upload_program(starmap_solver* s) {
+  ++s->graph_version;  // tiles, m ranges or LDS size may change: captured launches are stale
+  const TileShape ts = sweep_variant(s->variant);
+  s->nchunks = sweep_chunk_count(s->N, s->chunk_width);
+  for (int p = 0; p < 2; ++p) {
+    s->prog[p] = build_sweep_program(s->N, p, ts.tx, ts.ty, s->dx, s->dy, s->rows, s->dmap, s->qk, s->nchunks);
+    int rc = upload_one_program(s, s->prog[p], s->off_prog[p], s->prog_bytes[p]);
+    if (rc) return rc;
+  }
+  if (s->closure) {
+    // the same even program with the order-5 inputs read from the closure planes
+    SweepProgram pb = s->prog[0];
+    int a0 = -1, b0 = -1;
+    for (int k = 0; k < s->nmom; ++k)
+      if (s->moms[k].l == s->N) {
+        if (a0 < 0) {
+          a0 = k;
+          b0 = s->nmom + s->qk[k];
+        }
+        if (k - a0 != s->nmom + s->qk[k] - b0) return fail(STARMAP_EINVAL, "closure planes are not consecutive");
+      }
+    for (auto& ld : pb.loads)
+      if (ld.k >= a0 && ld.k < a0 + CLOSURE_OUT) ld.k = b0 + (ld.k - a0);
+    int rc = upload_one_program(s, pb, s->off_prog_b, s->prog_bytes[0]);
+    if (rc) return rc;
   }
   s->slots = std::max(s->prog[0].slots, s->prog[1].slots);
   s->prog_uploaded = true;
@@ -760,7 +788,10 @@ template <typename C>
 int launch_one(starmap_solver* s, int parity, double tau) {
   SweepArgs<C> a;
   const auto& pr = s->prog[parity];
-  char* base = dptr(s, s->off_prog[parity]);
+  // a fused closure solver's even sweep reads the order-5 moments where the
+  // last odd sweep wrote them
+  const bool from_b = parity == 0 && s->closure && s->closure_fused && s->c5_flip;
+  char* base = dptr(s, from_b ? s->off_prog_b : s->off_prog[parity]);
   size_t o = 0;
   a.chunks = reinterpret_cast<const int4*>(base + o);
   o += align256(pr.chunks.size() * 16);
@@ -785,6 +816,7 @@ int launch_one(starmap_solver* s, int parity, double tau) {
   a.nchunks = int(pr.chunks.size());
   a.zero_off = pr.zero_off;
   a.parity = parity;
+  a.strip = s->tile_strip;
   a.tau = C(tau);
   HIP_TRY(launch_sweep(s->storage, s->variant, &a, s->slots, s->stream));
   return STARMAP_OK;
@@ -793,7 +825,8 @@ int launch_one(starmap_solver* s, int parity, double tau) {
 double sweep_bytes_of(const starmap_solver* s, int parity);
 
 int sweep(starmap_solver* s, int parity, double tau, bool with_closure = true) {
-  if (parity == 1 && s->closure && with_closure) {
+  const bool fused_closure = parity == 1 && s->closure && with_closure && s->closure_fused;
+  if (parity == 1 && s->closure && with_closure && !s->closure_fused) {
     int rc = closure_before_odd(s);
     if (rc) return rc;
   }
@@ -807,13 +840,75 @@ int sweep(starmap_solver* s, int parity, double tau, bool with_closure = true) {
     }
     HIP_TRY(hipEventRecord(s->ev[s->ev_used], s->stream));
   }
-  int rc = s->storage == STORE_FP64 ? launch_one<double>(s, parity, tau) : launch_one<float>(s, parity, tau);
+  int rc = fused_closure ? closure_odd_sweep(s, tau)
+           : s->storage == STORE_FP64 ? launch_one<double>(s, parity, tau) : launch_one<float>(s, parity, tau);
   if (rc) return rc;
   if (s->profiling) {
     HIP_TRY(hipEventRecord(s->ev[s->ev_used + 1], s->stream));
     s->ev_used += 2;
     if (s->sweep_bytes_cache[parity] < 0) s->sweep_bytes_cache[parity] = sweep_bytes_of(s, parity);
     s->prof_bytes += s->sweep_bytes_cache[parity];
+  }
+  return STARMAP_OK;
+}
+
+// The even part of a step: S^e_tau, or S^e_{tau/2} D_tau S^e_{tau/2} with the
+// D_N diffusion step.
+int even_part(starmap_solver* s, double tau) {
+  if (!s->has_diffusion) return sweep(s, 0, tau);
+  int r = sweep(s, 0, 0.5 * tau);
+  if (!r) r = diffuse(s, tau);
+  if (!r) r = sweep(s, 0, 0.5 * tau);
+  return r;
+}
+
+void drop_pair_graphs(starmap_solver* s) {
+  for (auto& kv : s->pair_graphs) (void)hipGraphExecDestroy(kv.second);
+  s->pair_graphs.clear();
+}
+
+constexpr int kMaxGraphPairs = 16;
+
+// pairs times (S^e_dt, S^o_dt), as launches of captured graphs of 16, 8, 4,
+// 2 and 1 pairs (each captured on first use from the same calls the eager
+// path makes, so the kernels and their arguments are the same).
+int run_pairs_graphed(starmap_solver* s, int64_t pairs, double dt) {
+  if (s->pair_graphs_version != s->graph_version) {
+    drop_pair_graphs(s);
+    s->pair_graphs_version = s->graph_version;
+  }
+  while (pairs > 0) {
+    int p = kMaxGraphPairs;
+    while (p > pairs) p >>= 1;
+    // a fused closure solver's launches also depend on where the order-5
+    // moments sit (each odd sweep moves them)
+    const int key = 2 * p + s->c5_flip;
+    auto it = s->pair_graphs.find(key);
+    const bool cached = it != s->pair_graphs.end();
+    if (!cached) {
+      HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+      int rc = STARMAP_OK;
+      for (int i = 0; i < p && !rc; ++i) {
+        rc = even_part(s, dt);
+        if (!rc) rc = sweep(s, 1, dt);
+      }
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s->stream, &g);
+      if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) return rc;
+        HIP_TRY(e);
+      }
+      hipGraphExec_t x = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_TRY(ei);
+      it = s->pair_graphs.emplace(key, x).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, s->stream));
+    // the capture moved the host-side order-5 location already; a replay does it here
+    if (cached && s->closure && s->closure_fused) s->c5_flip ^= (p & 1);
+    pairs -= p;
   }
   return STARMAP_OK;
 }
@@ -976,6 +1071,7 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out) {
   s->pitch = int((s->nx + 1 + 63) / 64 * 64);
   s->nrows = s->ny + 1;
   s->plane_stride = (int64_t(s->pitch) * s->nrows + 127) / 128 * 128;
+  if (const char* e = std::getenv("STARMAP_TILE_STRIP")) s->tile_strip = std::max(1, std::atoi(e));
   // The kernels address a plane with 32-bit byte offsets (element offset
   // times the storage or compute size, whichever is larger): keep every such
   // offset below 2^31.
@@ -989,6 +1085,7 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out) {
 void starmap_destroy(starmap_solver* s) {
   if (!s) return;
   if (s->device_ready) (void)hipStreamSynchronize(s->stream);
+  drop_pair_graphs(s);
   if (s->sample_buf) (void)hipFree(s->sample_buf);
   if (s->owns_dev && s->dev) (void)hipFree(s->dev);
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
@@ -1220,14 +1317,7 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
   int rc = ensure_device(s);
   if (rc) return rc;
   const double dt = s->dt;
-  // the even part of a step: S^e_dt, or S^e_{dt/2} D_dt S^e_{dt/2} with the D_N diffusion step
-  auto even = [&]() -> int {
-    if (!s->has_diffusion) return sweep(s, 0, dt);
-    int r = sweep(s, 0, 0.5 * dt);
-    if (!r) r = diffuse(s, dt);
-    if (!r) r = sweep(s, 0, 0.5 * dt);
-    return r;
-  };
+  auto even = [&]() -> int { return even_part(s, dt); };
   if (!s->time_dependent && !s->separable && s->fused && !s->has_diffusion) {
     // pairs (S^o, S^e) in one pass each, ping-ponging between two state
     // buffers, then the closing odd half-step
@@ -1253,12 +1343,23 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
     }
     rc = sweep(s, 1, 0.5 * dt);
     if (rc) return rc;
-    for (int64_t i = 0; i < nsteps; ++i) {
-      rc = even();
+    // nsteps - 1 pairs (S^e_dt, S^o_dt), then S^e_dt, S^o_{dt/2}; the pairs
+    // replay captured graphs unless launches are being timed one by one (or
+    // the stream is the null stream, which cannot be captured)
+    const int64_t pairs = nsteps - 1;
+    if (pairs > 0 && s->use_graphs && !s->profiling && s->stream) {
+      rc = run_pairs_graphed(s, pairs, dt);
       if (rc) return rc;
-      rc = sweep(s, 1, i + 1 < nsteps ? dt : 0.5 * dt);
-      if (rc) return rc;
+    } else {
+      for (int64_t i = 0; i < pairs; ++i) {
+        rc = even();
+        if (!rc) rc = sweep(s, 1, dt);
+        if (rc) return rc;
+      }
     }
+    rc = even();
+    if (!rc) rc = sweep(s, 1, 0.5 * dt);
+    if (rc) return rc;
   } else if (s->separable && !s->time_dependent) {
     // time-separable data: decay and source planes formed on the device per step
     for (int64_t i = 0; i < nsteps; ++i) {
@@ -1283,6 +1384,10 @@ int starmap_advance(starmap_solver* s, int64_t nsteps) {
       rc = sweep(s, 1, 0.5 * dt);
       if (rc) return rc;
     }
+  }
+  if (s->closure) {
+    rc = closure_settle(s);
+    if (rc) return rc;
   }
   s->steps_done += nsteps;
   s->t = double(s->steps_done) * dt;
@@ -1309,6 +1414,7 @@ int starmap_sweep(starmap_solver* s, int32_t parity, double tau, int32_t nsweeps
     rc = sweep(s, parity, tau);
     if (rc) return rc;
   }
+  if (s->closure) return closure_settle(s);
   return STARMAP_OK;
 }
 
@@ -1435,6 +1541,13 @@ int starmap_set_variant(starmap_solver* s, int32_t v) {
     }
     return upload_program(s);
   }
+  return STARMAP_OK;
+}
+
+int starmap_set_graphs(starmap_solver* s, int32_t enable) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  s->use_graphs = enable != 0;
+  if (!s->use_graphs) drop_pair_graphs(s);
   return STARMAP_OK;
 }
 
@@ -1779,6 +1892,7 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
     e.nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
     e.nchunks = int(s->prog[0].chunks.size());
     e.nsweeps = sweeps[ord[r]];
+    e.strip = s->tile_strip;
     first[r] = int(total);
     total += items_of(s);
   }

@@ -111,6 +111,33 @@ int closure_geometry(const starmap_solver* s, ClosureGeo* g, bool with_terms) {
   return STARMAP_OK;
 }
 
+int closure_plane_a(const starmap_solver* s) { return s->cgeo.k[5]; }
+int closure_plane_b(const starmap_solver* s) { return s->nmom + s->qk[s->cgeo.k[5]]; }
+
+int closure_odd_sweep(starmap_solver* s, double tau) {
+  if (!s->closure_loaded) return fail(STARMAP_ESTATE, "learned closure: no network loaded (starmap_closure_load)");
+  const size_t pb = s->plane_bytes_state();
+  char* a = dptr(s, s->off_state + size_t(closure_plane_a(s)) * pb);
+  char* b = dptr(s, s->off_state + size_t(closure_plane_b(s)) * pb);
+  ClosureOdd odd = s->codd;
+  odd.tau = tau;
+  HIP_TRY(launch_closure_sweep(s->storage, dptr(s, s->off_state), s->c5_flip ? b : a, s->c5_flip ? a : b,
+                               dptr(s, s->off_decay), s->cgeo, reinterpret_cast<const ClosureNet*>(dptr(s, s->off_net)),
+                               odd, s->stream));
+  s->c5_flip ^= 1;
+  return STARMAP_OK;
+}
+
+int closure_settle(starmap_solver* s) {
+  if (!s->c5_flip) return STARMAP_OK;
+  const size_t pb = s->plane_bytes_state();
+  HIP_TRY(hipMemcpyAsync(dptr(s, s->off_state + size_t(closure_plane_a(s)) * pb),
+                         dptr(s, s->off_state + size_t(closure_plane_b(s)) * pb), CLOSURE_OUT * pb,
+                         hipMemcpyDeviceToDevice, s->stream));
+  s->c5_flip = 0;
+  return STARMAP_OK;
+}
+
 int closure_before_odd(starmap_solver* s) {
   if (!s->closure_loaded) return fail(STARMAP_ESTATE, "learned closure: no network loaded (starmap_closure_load)");
   HIP_TRY(launch_closure_infer(s->storage, dptr(s, s->off_state), dptr(s, s->off_decay), s->cgeo,
@@ -229,19 +256,62 @@ int starmap_closure_load(starmap_solver* s, const float* w, size_t count) {
   std::memcpy(net->b3, w + OFF_B3, CLOSURE_OUT * sizeof(float));
   HIP_TRY(hipMemcpyAsync(dptr(s, s->off_net), net.get(), sizeof(ClosureNet), hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  // the odd rows of the fused closure sweep
+  for (int o = 0; o < CLOSURE_OUT; ++o)
+    if (s->cgeo.k[5 + o] != s->cgeo.k[5] + o || s->qk[s->cgeo.k[5 + o]] != s->qk[s->cgeo.k[5]] + o)
+      return fail(STARMAP_EINVAL, "closure: order-5 planes are not consecutive");
+  std::memset(&s->codd, 0, sizeof(s->codd));
+  int q = 0;
+  for (int k = 0; k < s->nmom; ++k) {
+    const MomentInfo& mk = s->moms[k];
+    if (mk.l % 2 == 0) continue;
+    if (q >= CLOSURE_ODD_ROWS) return fail(STARMAP_EINVAL, "closure: too many odd moments");
+    ClosureOddRow& r = s->codd.r[q++];
+    r.k = k;
+    r.node_x = mk.gx == AXIS_NODE;
+    r.dk = s->dmap.dk[k];
+    r.o = mk.l == 5 ? k - s->cgeo.k[5] : -1;
+    r.src = (r.o < 0 && s->qk[k] >= 0) ? s->nmom + s->qk[k] : -1;
+    const CouplingRow& cr = s->rows[k];
+    r.nx = cr.nx;
+    r.ny = cr.ny;
+    for (int t = 0; t < cr.nx; ++t) {
+      r.xk[t] = cr.x[t].col;
+      r.xcell[t] = s->moms[cr.x[t].col].gx == AXIS_CELL;
+      r.xc[t] = -cr.x[t].val / s->dx;
+    }
+    for (int t = 0; t < cr.ny; ++t) {
+      r.yk[t] = cr.y[t].col;
+      r.ycell[t] = s->moms[cr.y[t].col].gy == AXIS_CELL;
+      r.yc[t] = -cr.y[t].val / s->dy;
+    }
+  }
+  if (q != CLOSURE_ODD_ROWS) return fail(STARMAP_EINVAL, "closure: unexpected number of odd moments");
   s->closure_loaded = true;
   return STARMAP_OK;
 }
 
-int starmap_closure_samples(starmap_solver* s, const int32_t* points, int32_t count, float* features,
-                            float* targets) {
-  if (!s || !points || !features || !targets || count < 0) return fail(STARMAP_EINVAL, "bad arguments");
+int starmap_closure_set_fused(starmap_solver* s, int32_t enable) {
+  if (!s) return fail(STARMAP_EINVAL, "solver is NULL");
+  if (!s->closure) return fail(STARMAP_ESTATE, "the solver was not created with STARMAP_CLOSURE_LEARNED");
+  int rc = closure_settle(s);
+  if (rc) return rc;
+  s->closure_fused = enable != 0;
+  ++s->graph_version;  // the launch sequence changes
+  return STARMAP_OK;
+}
+
+namespace {
+// Closure inputs (and, with targets, the order-6 flux) at cells of a solver's
+// current state; nu_out and targets may be null.
+int closure_points(starmap_solver* s, const int32_t* points, int32_t count, float* features, float* targets,
+                   float* nu_out) {
   if (count == 0) return STARMAP_OK;
   for (int32_t i = 0; i < count; ++i)
     if (points[2 * i] < 0 || points[2 * i] >= s->nx || points[2 * i + 1] < 0 || points[2 * i + 1] >= s->ny)
       return fail(STARMAP_EINVAL, "sample point outside the cells");
   ClosureGeo g;
-  int rc = closure_geometry(s, &g, true);
+  int rc = closure_geometry(s, &g, targets != nullptr);
   if (rc) return rc;
   rc = ensure_device(s);
   if (rc) return rc;
@@ -259,9 +329,23 @@ int starmap_closure_samples(starmap_solver* s, const int32_t* points, int32_t co
   }
   HIP_TRY(hipMemcpyAsync(s->sample_buf, points, bytes, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(launch_closure_samples(s->storage, dptr(s, s->off_state), dptr(s, s->off_decay), g,
-                                 static_cast<const int*>(s->sample_buf), count, features, targets, s->stream));
+                                 static_cast<const int*>(s->sample_buf), count, features, targets, nu_out,
+                                 s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return STARMAP_OK;
+}
+}  // namespace
+
+int starmap_closure_samples(starmap_solver* s, const int32_t* points, int32_t count, float* features,
+                            float* targets) {
+  if (!s || !points || !features || !targets || count < 0) return fail(STARMAP_EINVAL, "bad arguments");
+  return closure_points(s, points, count, features, targets, nullptr);
+}
+
+int starmap_closure_features(starmap_solver* s, const int32_t* points, int32_t count, float* features,
+                             float* nu) {
+  if (!s || !points || !features || count < 0) return fail(STARMAP_EINVAL, "bad arguments");
+  return closure_points(s, points, count, features, nullptr, nu);
 }
 
 int starmap_mlp_create(int32_t max_batch, void* hip_stream, starmap_mlp** out) {

@@ -86,6 +86,21 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   return start + idx;
 }
 
+// Tile number t -> tile column and row.  Tiles are numbered in strips of
+// `strip` tile rows, and within a strip column by column: consecutive tiles
+// are vertical neighbours (they share a halo row) and horizontal neighbours
+// are `strip` tiles apart, so with the XCD-contiguous block order both halos
+// of a tile are read while its neighbours' are still in that XCD's L2.
+// strip <= 1 numbers the tiles row by row.
+__device__ __forceinline__ int2 tile_xy(int t, int ntx, int nty, int strip) {
+  if (strip <= 1) return make_int2(t % ntx, t / ntx);
+  const int band = t / (strip * ntx);
+  const int row0 = band * strip;
+  const int rows = min(strip, nty - row0);
+  const int r = t - band * strip * ntx;
+  return make_int2(r / rows, row0 + r % rows);
+}
+
 // Kernel tables (sweep programs, coupling records) are read-only during a
 // launch and read at wave-uniform addresses: held as
 // constant-address-space pointers, those reads are scalar loads wherever the

@@ -26,6 +26,7 @@ struct SweepArgs {
   int nchunks;             // workgroups per tile (m ranges)
   int zero_off;            // LDS element offset of the zero plane
   int parity;              // 0: outputs on G11/G22, 1: outputs on G21/G12
+  int strip;               // tile rows per strip of the tile order (<= 1: row by row)
   C tau;                   // sub-step length
 };
 
@@ -59,7 +60,7 @@ struct BatchEntry {
   int pitch, nx, ny, px, py, ntx, nty, nchunks;
   int zero_off[2];
   int nsweeps;  // sweeps still to run: 2 n + 1 for n steps
-  int pad;
+  int strip;    // tile rows per strip of the tile order
 };
 
 // Opts the kernels of a variant in to the LDS it needs (outside any stream

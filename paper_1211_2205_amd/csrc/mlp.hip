@@ -258,12 +258,13 @@ __device__ __forceinline__ void sigma_inputs(const C* __restrict__ decay, const 
 
 // Training samples from a state of order >= 6: inputs (count x 128, FP32) and
 // targets F_k dx / nu (count x 6) at cells (i, j), one thread per sample.
+// targ may be null (inputs only); nu_out, if not null, receives nu per sample.
 template <typename T>
 __global__ void __launch_bounds__(256) closure_samples_kernel(const T* __restrict__ U,
                                                               const typename ComputeOf<T>::type* __restrict__ decay,
                                                               const ClosureGeo G, const int* __restrict__ pts,
                                                               int count, float* __restrict__ feat,
-                                                              float* __restrict__ targ) {
+                                                              float* __restrict__ targ, float* __restrict__ nu_out) {
   using C = typename ComputeOf<T>::type;
   const int s = blockIdx.x * 256 + threadIdx.x;
   if (s >= count) return;
@@ -291,6 +292,8 @@ __global__ void __launch_bounds__(256) closure_samples_kernel(const T* __restric
   f[q++] = float(fa);
   f[q++] = float(fs);
   for (; q < CLOSURE_IN; ++q) f[q] = 0.f;
+  if (nu_out) nu_out[s] = float(nu);
+  if (!targ) return;
   // targets: the order-6 part of the odd residual at the order-5 points
   for (int o = 0; o < CLOSURE_OUT; ++o) {
     const int X = internal_index(i, G.out_nodex[o], G.px, G.nx);
@@ -327,10 +330,44 @@ __global__ void __launch_bounds__(256) closure_samples_kernel(const T* __restric
 constexpr int CB = 64;               // evaluation points per block
 constexpr int LDW = CLOSURE_IN + 8;  // LDS row of one point's activations (bf16), padded
 
-template <typename T>
-__global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U,
+// The odd update of one odd moment of P_5 at the internal point (X, Y) of its
+// grid, with the couplings in the order of the sweep kernel (x terms, then y
+// terms), the source, then the closure term g: u + tau (W - c u) E(-c tau).
+template <typename T, typename C>
+__device__ __forceinline__ C closure_odd_update(const T* __restrict__ U, const ClosureOddRow& r, const ClosureGeo& G,
+                                                int X, int Y, C u, C g, C c, C E, C tau) {
+  const int64_t ps = G.plane_stride;
+  C W = C(0);
+  for (int t = 0; t < r.nx; ++t) {
+    const T* up = U + int64_t(r.xk[t]) * ps + int64_t(Y) * G.pitch;
+    const int lo = r.xcell[t] ? map_axis(X - 1, G.nx, G.px, 1) : map_axis(X, G.nx, G.px, 0);
+    const int hi = r.xcell[t] ? map_axis(X, G.nx, G.px, 1) : map_axis(X + 1, G.nx, G.px, 0);
+    W = couple(W, C(r.xc[t]), to_c(up[hi]), to_c(up[lo]));
+  }
+  for (int t = 0; t < r.ny; ++t) {
+    const T* up = U + int64_t(r.yk[t]) * ps + X;
+    const int lo = r.ycell[t] ? map_axis(Y - 1, G.ny, G.py, 1) : map_axis(Y, G.ny, G.py, 0);
+    const int hi = r.ycell[t] ? map_axis(Y, G.ny, G.py, 1) : map_axis(Y + 1, G.ny, G.py, 0);
+    W = couple(W, C(r.yc[t]), to_c(up[int64_t(hi) * G.pitch]), to_c(up[int64_t(lo) * G.pitch]));
+  }
+  if (r.src >= 0) W += to_c(U[int64_t(r.src) * ps + int64_t(Y) * G.pitch + X]);
+  if (r.o >= 0) W += g;
+  return sub_step(u, W, c, E, tau);
+}
+
+// FUSED = false: the closure terms g = nu y / dx of every evaluation point go
+// to the closure planes, which the odd sweep then reads like source planes.
+// FUSED = true: the same network, then the odd sweep of P_5 at the block's
+// points in the same workgroup (every odd moment at every evaluation point
+// that lies on its grid), the order-5 moments read from in5 and written to
+// out5 (out of place, so every workgroup's stencils see the state of the
+// start of the sweep), orders 1 and 3 in place (nothing else reads them).
+template <typename T, bool FUSED>
+__global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U, const T* __restrict__ in5,
+                                                            T* __restrict__ out5,
                                                             const typename ComputeOf<T>::type* __restrict__ decay,
-                                                            const ClosureGeo G, const ClosureNet* __restrict__ net) {
+                                                            const ClosureGeo G, const ClosureNet* __restrict__ net,
+                                                            const ClosureOdd odd) {
   using C = typename ComputeOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* Xa = reinterpret_cast<uint16_t*>(smem);  // [64][LDW] inputs, then layer-2 activations
@@ -339,6 +376,7 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
   C* nu_s = reinterpret_cast<C*>(W3 + 16 * LDW);     // [64]
   C* part = nu_s + CB;                                    // [4][64] partial sums of squares per wave
   int* otab = reinterpret_cast<int*>(part + 4 * CB);  // [5][8] output plane, extents, nodal flags
+  C* gsh = reinterpret_cast<C*>(otab + 5 * 8);        // FUSED: [6][64] closure terms of the block
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int fk = 8 * (lane >> 4);
 
@@ -405,7 +443,7 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
     for (int t = 0; t < 3; ++t) {
       const int p = w + 4 * t;
       if (p < CLOSURE_PLANES) {
-        const T* up = U + int64_t(G.k[p]) * G.plane_stride;
+        const T* up = p < 5 ? U + int64_t(G.k[p]) * G.plane_stride : in5 + int64_t(p - 5) * G.plane_stride;
         const int cx = G.nodex[p], cy = G.nodey[p];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -418,7 +456,7 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
     // norm is reduced across the waves
     C v0[9];
     {
-      const T* up = U + int64_t(G.k[w]) * G.plane_stride;
+      const T* up = U + int64_t(G.k[w]) * G.plane_stride;  // w < 4: an order-4 plane
       const int cx = G.nodex[w], cy = G.nodey[w];
 #pragma unroll
       for (int q = 0; q < 9; ++q) v0[q] = to_c(up[rowy[cy][q / 3] + colx[cx][q % 3]]);
@@ -434,7 +472,7 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
     for (int t = 1; t < 3; ++t) {
       const int p = w + 4 * t;
       if (p < CLOSURE_PLANES) {
-        const T* up = U + int64_t(G.k[p]) * G.plane_stride;
+        const T* up = p < 5 ? U + int64_t(G.k[p]) * G.plane_stride : in5 + int64_t(p - 5) * G.plane_stride;
         const int cx = G.nodex[p], cy = G.nodey[p];
         // all nine loads first, so they are in flight together
         C v[9];
@@ -501,16 +539,57 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
     }
     const int m = 16 * w + (lane & 15);  // point of this lane
     const int p2 = blk * CB + m;
-    if (p2 < total) {
-      const int pi = p2 % NXE, pj = p2 / NXE;
+    if (!FUSED) {
+      if (p2 < total) {
+        const int pi = p2 % NXE, pj = p2 / NXE;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int o = 4 * (lane >> 4) + r;  // output of this lane
-        if (o >= CLOSURE_OUT || pi >= otab[8 + o] || pj >= otab[16 + o]) continue;
-        const int X = internal_index(pi, otab[24 + o], G.px, G.nx);
-        const int Y = internal_index(pj, otab[32 + o], G.py, G.ny);
-        const C g = nu_s[m] * C(y[r] + b3[r]) / C(G.dx);
-        U[int64_t(otab[o]) * G.plane_stride + int64_t(Y) * G.pitch + X] = from_c<T>(g);
+        for (int r = 0; r < 4; ++r) {
+          const int o = 4 * (lane >> 4) + r;  // output of this lane
+          if (o >= CLOSURE_OUT || pi >= otab[8 + o] || pj >= otab[16 + o]) continue;
+          const int X = internal_index(pi, otab[24 + o], G.px, G.nx);
+          const int Y = internal_index(pj, otab[32 + o], G.py, G.ny);
+          const C g = nu_s[m] * C(y[r] + b3[r]) / C(G.dx);
+          U[int64_t(otab[o]) * G.plane_stride + int64_t(Y) * G.pitch + X] = from_c<T>(g);
+        }
+      }
+      continue;
+    }
+    // 4. (fused) the closure terms of the block into LDS, then the odd update:
+    // wave w takes odd rows w, w + 4, w + 8, lane = point of the block
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 4 * (lane >> 4) + r;
+      if (o < CLOSURE_OUT) gsh[o * CB + m] = nu_s[m] * C(y[r] + b3[r]) / C(G.dx);
+    }
+    __syncthreads();
+    if (pt < total) {  // the point of this lane: (i, j) of the gather above
+      // decay and E(-c tau) per output grid, reloaded when a row's decay plane differs
+      int dk21 = -1, dk12 = -1;
+      C c21 = C(0), e21 = C(0), c12 = C(0), e12 = C(0);
+      const int w0 = __builtin_amdgcn_readfirstlane(w);
+      for (int q = w0; q < CLOSURE_ODD_ROWS; q += 4) {
+        const ClosureOddRow& r = odd.r[q];
+        const int nd = r.node_x;
+        // the row's grid: G21 has nx + 1 - px by ny points, G12 nx by ny + 1 - py
+        if (nd ? (i >= G.nx + 1 - G.px || j >= G.ny) : (i >= G.nx || j >= G.ny + 1 - G.py)) continue;
+        const int X = nd ? internal_index(i, 1, G.px, G.nx) : i;
+        const int Y = nd ? j : internal_index(j, 1, G.py, G.ny);
+        const int64_t off = int64_t(Y) * G.pitch + X;
+        if (nd && r.dk != dk21) {
+          c21 = decay[int64_t(r.dk) * G.plane_stride + off];
+          e21 = expm1div(-c21 * C(odd.tau));
+          dk21 = r.dk;
+        } else if (!nd && r.dk != dk12) {
+          c12 = decay[int64_t(r.dk) * G.plane_stride + off];
+          e12 = expm1div(-c12 * C(odd.tau));
+          dk12 = r.dk;
+        }
+        const T* src = r.o >= 0 ? in5 + int64_t(r.o) * G.plane_stride : U + int64_t(r.k) * G.plane_stride;
+        const C u = to_c(src[off]);
+        const C g = r.o >= 0 ? gsh[r.o * CB + lane] : C(0);
+        const C v = closure_odd_update(U, r, G, X, Y, u, g, nd ? c21 : c12, nd ? e21 : e12, C(odd.tau));
+        T* dst = r.o >= 0 ? out5 + int64_t(r.o) * G.plane_stride : U + int64_t(r.k) * G.plane_stride;
+        dst[off] = from_c<T>(v);
       }
     }
   }
@@ -557,20 +636,20 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 }
 
 hipError_t launch_closure_samples(int storage, const void* U, const void* decay, const ClosureGeo& G,
-                                  const int* pts, int count, float* feat, float* targ, hipStream_t stream) {
+                                  const int* pts, int count, float* feat, float* targ, float* nu, hipStream_t stream) {
   const dim3 grid((count + 255) / 256);
   switch (storage) {
     case STORE_FP64:
       hipLaunchKernelGGL(closure_samples_kernel<double>, grid, dim3(256), 0, stream,
-                         static_cast<const double*>(U), static_cast<const double*>(decay), G, pts, count, feat, targ);
+                         static_cast<const double*>(U), static_cast<const double*>(decay), G, pts, count, feat, targ, nu);
       break;
     case STORE_FP32:
       hipLaunchKernelGGL(closure_samples_kernel<float>, grid, dim3(256), 0, stream,
-                         static_cast<const float*>(U), static_cast<const float*>(decay), G, pts, count, feat, targ);
+                         static_cast<const float*>(U), static_cast<const float*>(decay), G, pts, count, feat, targ, nu);
       break;
     case STORE_BF16:
       hipLaunchKernelGGL(closure_samples_kernel<bf16>, grid, dim3(256), 0, stream,
-                         static_cast<const bf16*>(U), static_cast<const float*>(decay), G, pts, count, feat, targ);
+                         static_cast<const bf16*>(U), static_cast<const float*>(decay), G, pts, count, feat, targ, nu);
       break;
     default:
       return hipErrorInvalidValue;
@@ -579,32 +658,30 @@ hipError_t launch_closure_samples(int storage, const void* U, const void* decay,
 }
 
 size_t closure_infer_lds_bytes() {
-  return size_t(2 * CB + 16) * LDW * 2 + size_t(5 * CB) * 8 + 5 * 8 * sizeof(int);
+  return size_t(2 * CB + 16) * LDW * 2 + size_t(5 * CB) * 8 + 5 * 8 * sizeof(int) + size_t(CLOSURE_OUT * CB) * 8;
 }
 
 namespace {
-template <typename T>
-hipError_t launch_infer_t(void* U, const void* decay, const ClosureGeo& G, const ClosureNet* net, int blocks,
-                          hipStream_t stream) {
+template <typename T, bool FUSED>
+hipError_t launch_infer_t(void* U, const void* in5, void* out5, const void* decay, const ClosureGeo& G,
+                          const ClosureNet* net, const ClosureOdd& odd, int blocks, hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   static bool attr = false;
   const size_t lds = closure_infer_lds_bytes();
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&closure_infer_kernel<T>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&closure_infer_kernel<T, FUSED>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(closure_infer_kernel<T>, dim3(blocks), dim3(256), lds, stream, static_cast<T*>(U),
-                     static_cast<const C*>(decay), G, net);
+  hipLaunchKernelGGL((closure_infer_kernel<T, FUSED>), dim3(blocks), dim3(256), lds, stream, static_cast<T*>(U),
+                     static_cast<const T*>(in5), static_cast<T*>(out5), static_cast<const C*>(decay), G, net, odd);
   return hipGetLastError();
 }
-}  // namespace
 
-hipError_t launch_closure_infer(int storage, void* U, const void* decay, const ClosureGeo& G, const ClosureNet* net,
-                                hipStream_t stream) {
-  // a few workgroups per compute unit, each looping over blocks of points
-  // with the weights loaded once
+// a few workgroups per compute unit, each looping over blocks of points with
+// the weights loaded once
+int infer_blocks(const ClosureGeo& G) {
   static int cus = 0;
   if (!cus) {
     int dev = 0;
@@ -614,11 +691,43 @@ hipError_t launch_closure_infer(int storage, void* U, const void* decay, const C
   }
   const int total = (G.nx + 1) * (G.ny + 1);
   const int nblk = (total + CB - 1) / CB;
-  const int blocks = std::min(nblk, 3 * cus);
+  return std::min(nblk, 3 * cus);
+}
+}  // namespace
+
+hipError_t launch_closure_infer(int storage, void* U, const void* decay, const ClosureGeo& G, const ClosureNet* net,
+                                hipStream_t stream) {
+  const int blocks = infer_blocks(G);
+  ClosureOdd none{};
+  // the order-5 inputs sit in U (moments G.k[5 ..], consecutive)
   switch (storage) {
-    case STORE_FP64: return launch_infer_t<double>(U, decay, G, net, blocks, stream);
-    case STORE_FP32: return launch_infer_t<float>(U, decay, G, net, blocks, stream);
-    case STORE_BF16: return launch_infer_t<bf16>(U, decay, G, net, blocks, stream);
+    case STORE_FP64: {
+      double* u = static_cast<double*>(U);
+      return launch_infer_t<double, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net, none,
+                                           blocks, stream);
+    }
+    case STORE_FP32: {
+      float* u = static_cast<float*>(U);
+      return launch_infer_t<float, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net, none,
+                                          blocks, stream);
+    }
+    case STORE_BF16: {
+      bf16* u = static_cast<bf16*>(U);
+      return launch_infer_t<bf16, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net, none,
+                                         blocks, stream);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_closure_sweep(int storage, void* U, const void* in5, void* out5, const void* decay,
+                                const ClosureGeo& G, const ClosureNet* net, const ClosureOdd& odd,
+                                hipStream_t stream) {
+  const int blocks = infer_blocks(G);
+  switch (storage) {
+    case STORE_FP64: return launch_infer_t<double, true>(U, in5, out5, decay, G, net, odd, blocks, stream);
+    case STORE_FP32: return launch_infer_t<float, true>(U, in5, out5, decay, G, net, odd, blocks, stream);
+    case STORE_BF16: return launch_infer_t<bf16, true>(U, in5, out5, decay, G, net, odd, blocks, stream);
   }
   return hipErrorInvalidValue;
 }

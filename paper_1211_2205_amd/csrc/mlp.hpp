@@ -51,6 +51,26 @@ struct ClosureGeo {
   ClosureTerm term[CLOSURE_OUT][4];
 };
 
+// The odd sweep of a P_5 closure solver fused with the closure network: one
+// row per odd moment (orders 1, 3, 5), with its couplings to the even moments
+// in the order of the rows of M_x, then M_y, and their coefficients
+// -M(k, j) / dx, -M(k, j) / dy.
+struct ClosureOddRow {
+  int k;        // plane of the moment (orders 1 and 3: updated in place)
+  int node_x;   // 1: grid G21 (nodal in x, cell-centred in y); 0: grid G12
+  int dk;       // decay plane
+  int src;      // source plane (absolute plane index) or -1
+  int o;        // order-5 output index 0..5 (read and written through the order-5 buffers), or -1
+  int nx, ny;   // couplings along x and y
+  int xk[4], xcell[4], yk[4], ycell[4];  // input plane; 1 if the input is cell-centred along the axis
+  double xc[4], yc[4];
+};
+constexpr int CLOSURE_ODD_ROWS = 12;
+struct ClosureOdd {
+  ClosureOddRow r[CLOSURE_ODD_ROWS];
+  double tau;
+};
+
 struct GemmArgs {
   const float* A;
   int64_t sam, sak;
@@ -83,8 +103,16 @@ hipError_t launch_mse(const float* Y, const float* T, int64_t count, float* dY, 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t stream);
 hipError_t launch_closure_samples(int storage, const void* U, const void* decay, const ClosureGeo& G,
-                                  const int* pts, int count, float* feat, float* targ, hipStream_t stream);
+                                  const int* pts, int count, float* feat, float* targ, float* nu,
+                                  hipStream_t stream);
 hipError_t launch_closure_infer(int storage, void* U, const void* decay, const ClosureGeo& G, const ClosureNet* net,
+                                hipStream_t stream);
+// The odd sweep of a P_5 closure solver with the network evaluated in the same
+// kernel: reads the order-5 moments from in5 (plane r of output r at
+// in5 + r * plane_stride) and writes their updates to out5; updates the
+// orders 1 and 3 in place.
+hipError_t launch_closure_sweep(int storage, void* U, const void* in5, void* out5, const void* decay,
+                                const ClosureGeo& G, const ClosureNet* net, const ClosureOdd& odd,
                                 hipStream_t stream);
 size_t closure_infer_lds_bytes();
 

@@ -112,8 +112,16 @@ struct starmap_solver {
   int slots = 0;
   int nchunks = 1;               // m ranges per tile (workgroups per tile and sweep)
   int chunk_width = 0;           // m indices per range (0: default)
+  int tile_strip = 8;            // tile rows per strip of the sweep's tile order
   starmap::SweepProgram prog[2];
   bool prog_uploaded = false;
+
+  // HIP graphs of runs of the repeated pair (S^e_dt, S^o_dt) of the plain
+  // composition, one per power-of-two pair count; dropped whenever the launch
+  // sequence may change (graph_version, bumped by upload_program)
+  bool use_graphs = true;
+  int graph_version = 0, pair_graphs_version = -1;
+  std::map<int, hipGraphExec_t> pair_graphs;
 
   // per-launch HIP events of the sweep kernel (starmap_profile_begin/end)
   bool profiling = false;
@@ -125,6 +133,14 @@ struct starmap_solver {
   // learned closure (order 5): network region, geometry, weights loaded
   bool closure = false;
   bool closure_loaded = false;
+  // fused closure sweep (default): the order-5 moments alternate between their
+  // state planes (A) and the closure planes (B); c5_flip = 1 while the current
+  // values sit in B (only between the odd sweeps of one advance call); the
+  // even sweep then reads them through a second program (off_prog_b)
+  bool closure_fused = true;
+  int c5_flip = 0;
+  size_t off_prog_b = 0;
+  starmap::ClosureOdd codd{};
   size_t off_net = 0;
   starmap::ClosureGeo cgeo{};
   void* sample_buf = nullptr;  // device copy of training-sample points
@@ -174,6 +190,13 @@ int max_lds_bytes();
 // fused closure kernel run before every odd sweep of a closure solver.
 int closure_geometry(const starmap_solver* s, ClosureGeo* g, bool with_terms);
 int closure_before_odd(starmap_solver* s);
+// Fused closure solvers: the odd sweep with the network (flips c5_flip), and
+// the copy that puts the order-5 moments back into their state planes.
+int closure_odd_sweep(starmap_solver* s, double tau);
+int closure_settle(starmap_solver* s);
+// First plane of the order-5 moments in A (state) and in B (closure planes).
+int closure_plane_a(const starmap_solver* s);
+int closure_plane_b(const starmap_solver* s);
 
 }  // namespace detail
 }  // namespace starmap

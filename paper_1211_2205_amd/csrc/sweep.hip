@@ -34,7 +34,7 @@ namespace starmap {
 template <typename C>
 struct SweepScalars {
   uint32_t ps;  // plane stride in elements
-  int pitch, nx, ny, px, py, ntx, nty, nchunks, zero_off, parity;
+  int pitch, nx, ny, px, py, ntx, nty, nchunks, zero_off, parity, strip;
   C tau;
 };
 
@@ -98,8 +98,9 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   const int tile = lb / a.nchunks;
   const int4 chk = rec4(chunks, lb - tile * a.nchunks);
   if (chk.x >= chk.y) return;  // no output rows in this m range
-  const int x0 = (tile % a.ntx) * TX;
-  const int y0 = (tile / a.ntx) * TY;
+  const int2 txy = tile_xy(tile, a.ntx, a.nty, a.strip);
+  const int x0 = txy.x * TX;
+  const int y0 = txy.y * TY;
   const int grp = 0;
 
   // Staging of one input plane into its (TX+1) x (TY+1) LDS tile.  The tile
@@ -408,7 +409,7 @@ struct BatchEntryG {
   int pitch, nx, ny, px, py, ntx, nty, nchunks;
   int zero_off[2];
   int nsweeps;
-  int pad;
+  int strip;
 };
 static_assert(sizeof(BatchEntryG) == sizeof(BatchEntry), "device view of BatchEntry");
 static_assert(offsetof(BatchEntryG, plane_stride) == offsetof(BatchEntry, plane_stride), "device view of BatchEntry");
@@ -439,6 +440,7 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
   a.nchunks = e.nchunks;
   a.zero_off = e.zero_off[par];
   a.parity = par;
+  a.strip = e.strip;
   a.tau = C((j == 0 || j == e.nsweeps - 1) ? e.tau_half : e.tau_full);
   sweep_tile<T, TX, TY, CAP>((T*)(gptr<T>)e.u, (const C*)(gptr<const C>)e.decay, (cptr<int>)e.chunks[par],
                              (cptr<int>)e.orders[par], (cptr<int>)e.loads[par], (cptr<int>)e.rows[par],
@@ -500,6 +502,7 @@ hipError_t launch_t(const void* args, int slots, hipStream_t stream) {
   sc.nchunks = a.nchunks;
   sc.zero_off = a.zero_off;
   sc.parity = a.parity;
+  sc.strip = a.strip;
   sc.tau = a.tau;
   const int blocks = a.ntx * a.nty * a.nchunks;
   hipLaunchKernelGGL((sweep_kernel<T, TX, TY, CAP>), dim3(blocks), dim3(256), lds, stream,

@@ -301,6 +301,20 @@ class Solver:
                                                 ctypes.c_void_p(features.data_ptr()),
                                                 ctypes.c_void_p(targets.data_ptr())))
 
+    def closure_features(self, points, features, nu=None):
+        """Closure inputs (and the stencil norms nu) at cells points[r] = (i, j)
+        of this (order >= 5) solver's current state, into float32 device
+        tensors features (count x 128) and nu (count)."""
+        pts = np.ascontiguousarray(points, dtype=np.int32).reshape(-1, 2)
+        n = pts.shape[0]
+        assert features.is_cuda and features.is_contiguous() and str(features.dtype) == "torch.float32"
+        assert features.numel() >= n * 128
+        if nu is not None:
+            assert nu.is_cuda and nu.is_contiguous() and str(nu.dtype) == "torch.float32" and nu.numel() >= n
+        B.check(B.lib().starmap_closure_features(self._h, pts.ctypes.data_as(B._i32p), n,
+                                                 ctypes.c_void_p(features.data_ptr()),
+                                                 ctypes.c_void_p(nu.data_ptr() if nu is not None else 0)))
+
     def reset(self):
         """Back to the initial condition at t = 0."""
         B.check(B.lib().starmap_reset(self._h))
@@ -351,6 +365,14 @@ class Solver:
 
     def autotune(self, sweeps=3):
         B.check(B.lib().starmap_autotune(self._h, int(sweeps)))
+
+    def set_closure_fused(self, enable):
+        """Closure solvers: network and odd sweep in one kernel (True) or two."""
+        B.check(B.lib().starmap_closure_set_fused(self._h, 1 if enable else 0))
+
+    def set_graphs(self, enable):
+        """Replay the repeated sweep pairs of advance() from captured HIP graphs."""
+        B.check(B.lib().starmap_set_graphs(self._h, 1 if enable else 0))
 
     def set_chunk_width(self, width):
         """m-range width of the sweep (4, 6 or 8)."""

