@@ -136,6 +136,20 @@ def batch_leg(count, precision):
     return out
 
 
+def closure_leg(count):
+    """The learned closure (held-out random media 256^2, FP32): zeroth-moment
+    error of plain P_5, plain P_9 and P_5 + closure against P_31, and the time
+    of each model's batch of `count` instances (one graph launch)."""
+    import numpy as np
+
+    from paper_1211_2205_amd import closure_eval
+    w = np.load(os.path.join(ROOT, "paper_1211_2205_amd", "weights", "closure_p5_256.npy"),
+                allow_pickle=False).astype(np.float32)
+    summary, _ = closure_eval.evaluate(w, range(2000, 2000 + count), singles=0, log=lambda m: None)
+    summary["workload"] = f"closure_P5_256_heldout_{count}_fp32"
+    return summary
+
+
 def models_leg(config, precision, steps):
     """The moment models of the paper's outlook on the same workload: plain
     P_N, filtered P_N (damping 10 (l/(N+1))^4 per order: the decay planes
@@ -405,6 +419,8 @@ def main():
     ap.add_argument("--fused-cells", default="1000,2048", help="grid sizes n (n x n) of the parity-fused leg")
     ap.add_argument("--models-steps", type=int, default=20,
                     help="timed steps of the FP_N / D_N model leg (0: skip it)")
+    ap.add_argument("--closure", type=int, default=16,
+                    help="held-out instances of the learned-closure leg (0: skip it)")
     ap.add_argument("--ceiling-gib", type=float, default=2.0,
                     help="array size of the streaming-ceiling leg (torch copy and add; 0: skip it)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
@@ -492,6 +508,8 @@ def main():
                         for N in args.fused_orders.split(",") for n in args.fused_cells.split(",")]
     if args.batch > 0:
         out["batch"] = batch_leg(args.batch, "fp32")
+    if args.closure > 0:
+        out["closure"] = closure_leg(args.closure)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -318,17 +318,19 @@ int starmap_profile_end(starmap_solver* s, double* kernel_ms, int64_t* launches,
    precede the first advance of a closure solver. */
 int starmap_closure_load(starmap_solver* s, const float* weights, size_t count);
 
-/* How the closure enters the odd sweep.  enable = 1 (default): one kernel
-   evaluates the network on blocks of 64 evaluation points and applies the
-   odd sub-step of P_5 to those points in the same workgroup; the order-5
-   moments are read from one buffer and written to a second one (the state
-   planes and the closure planes take turns; every call leaves them in the
-   state planes), so every stencil sees the state at the start of the sweep.
-   enable = 0: a network kernel writes the closure terms to the closure planes
-   and the odd sweep kernel reads them like sources.  Both give the same
-   bits for FP64 and FP32 storage (with BF16 storage, 0 rounds the closure
-   terms to bfloat16 on the way through the closure planes).
-   STARMAP_ESTATE if the solver is not a closure solver. */
+/* How the closure enters the odd sweep of this solver's own runs.
+   enable = 1: one kernel evaluates the network on blocks of 64 evaluation
+   points and applies the odd sub-step of P_5 to those points in the same
+   workgroup; the order-5 moments are read from one buffer and written to a
+   second one (the state planes and the closure planes take turns; every call
+   leaves them in the state planes), so every stencil sees the state at the
+   start of the sweep.  enable = 0 (default; faster for one instance on
+   MI355X): a network kernel writes the closure terms to the closure planes and
+   the odd sweep kernel reads them like sources.  Both give the same bits for
+   FP64 and FP32 storage (with BF16 storage, 0 rounds the closure terms to
+   bfloat16 on the way through the closure planes).  Batches of closure
+   solvers always use the fused kernel.  STARMAP_ESTATE if the solver is not a
+   closure solver. */
 int starmap_closure_set_fused(starmap_solver* s, int32_t enable);
 
 /* Training samples from the current state of a solver of order N >= 6
@@ -466,7 +468,10 @@ int starmap_reset(starmap_solver* s);
    and step counts share the machine, and a whole run is captured in one HIP
    graph.  The solvers must share the storage precision, have time-independent
    data, and outlive the batch; their results are read with the per-solver
-   calls.  While in a batch, a solver's tile variant is the batch's: do not
+   calls.  A batch holds either no closure solvers or only closure solvers
+   (STARMAP_CLOSURE_LEARNED, network loaded, one network for all): then every
+   odd sweep is one launch of the fused closure kernel (see
+   starmap_closure_set_fused) over all running instances.  While in a batch, a solver's tile variant is the batch's: do not
    call starmap_set_variant on it. */
 typedef struct starmap_batch starmap_batch;
 

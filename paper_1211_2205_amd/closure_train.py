@@ -8,12 +8,18 @@ random cells, extracted by the library's sample kernel.
 
 Training: the library's network trainer (BF16-MFMA forward and backward,
 Adam), mean squared error, cosine learning-rate decay, a held-out fraction of
-the samples for validation.  The closure is fitted to snapshots of the
-high-order solution (a-priori), but acts inside the P_5 scheme on P_5 states,
-where at full strength it can amplify grid-scale modes (it is a centred,
-explicitly integrated flux term of the order-5 moments themselves); the output
-layer is therefore scaled by a factor alpha chosen a posteriori on training
-instances.  Writes the FP32 parameter blob (.npy) and a JSON log.
+the samples for validation.  The closure is first fitted to snapshots of the
+high-order solution (a-priori).  It acts, however, inside the P_5 scheme on
+P_5 states, which drift from the truncated high-order states; so in rounds of
+"closure in the loop" (--loop-rounds) the current network runs inside P_5 on
+training instances next to the high-order run, and the P_5 + closure states
+at the snapshot times become further inputs, paired with the high-order
+run's order-6 flux at the same cells (rescaled to the P_5 stencil norm),
+before the network is trained further on all samples.  At full strength the
+closure can still amplify grid-scale modes (it is a centred, explicitly
+integrated flux term of the order-5 moments themselves); the output layer is
+therefore scaled by a factor alpha chosen a posteriori on training instances.
+Writes the FP32 parameter blob (.npy) and a JSON log.
 
     python -m paper_1211_2205_amd.closure_train --out weights.npy
 """
@@ -80,7 +86,61 @@ def generate(runs, n, order, snapshots, per_snapshot, seed, log=print):
     return X, T
 
 
-def train(X, T, epochs, batch, lr, seed, val_fraction=0.02, log=print):
+def generate_loop(params, runs, first, n, order, snapshots, per_snapshot, seed, log=print):
+    """Inputs from P_5 + closure states (network `params` as it acts in the
+    solver) and targets from the order-`order` run of the same instance at
+    the same snapshot fractions of t_final and the same cells: the high-order
+    run's order-6 flux F dx / nu_high, rescaled by nu_high / nu_5 to the P_5
+    inputs' normalisation."""
+    import torch
+
+    import paper_1211_2205_amd as pa
+    import workloads as wl
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    total = runs * snapshots * per_snapshot
+    X = torch.empty((total, N_IN), dtype=torch.float32, device="cuda")
+    T = torch.empty((total, N_OUT), dtype=torch.float32, device="cuda")
+    Xh = torch.empty((per_snapshot, N_IN), dtype=torch.float32, device="cuda")
+    nu5 = torch.empty(per_snapshot, dtype=torch.float32, device="cuda")
+    nuh = torch.empty(per_snapshot, dtype=torch.float32, device="cuda")
+    off = 0
+    t0 = time.time()
+    unstable = 0
+    for r in range(first, first + runs):
+        hi = pa.Solver.from_problem(wl.closure_instance(r, order, n), precision="fp32")
+        lo = pa.Solver.from_problem(wl.closure_instance(r, 5, n), precision="fp32", closure="learned")
+        hi.bind_torch()
+        lo.bind_torch()
+        lo.load_closure(params)
+        done_h = done_l = 0
+        for q in range(snapshots):
+            ch = round(hi.nsteps * (q + 1) / snapshots)
+            cl = round(lo.nsteps * (q + 1) / snapshots)
+            hi.advance(ch - done_h)
+            lo.advance(cl - done_l)
+            done_h, done_l = ch, cl
+            pts = rng.integers(0, n, size=(per_snapshot, 2)).astype(np.int32)
+            sl = slice(off, off + per_snapshot)
+            lo.closure_features(pts, X[sl], nu5)
+            hi.closure_samples(pts, Xh, T[sl])
+            hi.closure_features(pts, Xh, nuh)
+            T[sl] *= (nuh / nu5).unsqueeze(1)
+            off += per_snapshot
+        bad = not bool(torch.isfinite(X[off - snapshots * per_snapshot:off]).all())
+        if bad:  # a run that lost finiteness contributes nothing
+            unstable += 1
+            off -= snapshots * per_snapshot
+        hi.close()
+        lo.close()
+        if (r - first + 1) % 100 == 0:
+            log(f"closure loop data: {r - first + 1}/{runs} runs, {off} samples, {time.time() - t0:.1f} s")
+    log(f"closure loop data: {runs} runs from instance {first}, {off} samples ({unstable} unstable runs dropped), "
+        f"{time.time() - t0:.1f} s")
+    return X[:off], T[:off]
+
+
+def train(X, T, epochs, batch, lr, seed, val_fraction=0.02, log=print, init=None):
     import torch
 
     import paper_1211_2205_amd as pa
@@ -93,7 +153,7 @@ def train(X, T, epochs, batch, lr, seed, val_fraction=0.02, log=print):
     val, tr = perm[:nval], perm[nval:]
     Xv, Tv = X[val[:batch]].contiguous(), T[val[:batch]].contiguous()
     net = pa.MLP(batch)
-    net.set_params(init_params(seed))
+    net.set_params(init_params(seed) if init is None else init)
     steps_per_epoch = tr.numel() // batch
     total = epochs * steps_per_epoch
     hist = []
@@ -172,28 +232,52 @@ def main(argv=None):
     ap.add_argument("--calibrate-runs", type=int, default=8,
                     help="training instances (indices 0..k-1) for the a-posteriori output scale")
     ap.add_argument("--alphas", default="0.3,0.4,0.5,0.6,0.7,0.8,1.0")
+    ap.add_argument("--loop-rounds", type=int, default=2, help="rounds of training on P_5 + closure states")
+    ap.add_argument("--loop-runs", type=int, default=400, help="training instances per loop round")
+    ap.add_argument("--loop-epochs", type=int, default=3)
+    ap.add_argument("--loop-lr", type=float, default=5e-4)
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
+
+    import torch
 
     t0 = time.time()
     X, T = generate(args.runs, args.n, args.order, args.snapshots, args.per_snapshot, args.seed, log)
     t1 = time.time()
     params, hist = train(X, T, args.epochs, args.batch, args.lr, args.seed, log=log)
     nsamples = int(X.shape[0])
-    del X, T
     t2 = time.time()
+    alphas = [float(a) for a in args.alphas.split(",")]
     alpha, table = 1.0, []
     if args.calibrate_runs > 0:
-        alphas = [float(a) for a in args.alphas.split(",")]
         alpha, table = calibrate(params, range(args.calibrate_runs), args.n, args.order, alphas, log)
-        params = scale_output(params, alpha)
+    loops = []
+    for rnd in range(args.loop_rounds):
+        # the network as it acts in the solver (scaled by the current alpha)
+        # produces the states; the raw network is trained further on them
+        first = args.calibrate_runs + rnd * args.loop_runs
+        Xl, Tl = generate_loop(scale_output(params, alpha), args.loop_runs, first, args.n, args.order,
+                               args.snapshots, args.per_snapshot, args.seed + 1 + rnd, log)
+        X, T = torch.cat([X, Xl]), torch.cat([T, Tl])
+        del Xl, Tl
+        params, h = train(X, T, args.loop_epochs, args.batch, args.loop_lr, args.seed + 1 + rnd, log=log,
+                          init=params)
+        a, tab = (calibrate(params, range(args.calibrate_runs), args.n, args.order, alphas, log)
+                  if args.calibrate_runs > 0 else (1.0, []))
+        loops.append({"round": rnd, "first_instance": first, "samples": int(X.shape[0]), "history": h,
+                      "alpha": a, "calibration": tab})
+        alpha, table = a, tab
+    nsamples = int(X.shape[0])
+    del X, T
+    t3 = time.time()
+    params = scale_output(params, alpha)
     np.save(args.out, params)
     meta = {"runs": args.runs, "n": args.n, "order": args.order, "snapshots": args.snapshots,
             "per_snapshot": args.per_snapshot, "samples": nsamples, "epochs": args.epochs,
             "batch": args.batch, "lr": args.lr, "seed": args.seed, "data_s": t1 - t0, "train_s": t2 - t1,
-            "history": hist, "alpha": alpha, "calibration": table}
+            "loop_s": t3 - t2, "history": hist, "loop_rounds": loops, "alpha": alpha, "calibration": table}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
     log(f"closure train: wrote {args.out} (alpha {alpha}; data {t1 - t0:.1f} s, training {t2 - t1:.1f} s)")

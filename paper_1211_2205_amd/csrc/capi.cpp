@@ -1765,6 +1765,11 @@ struct starmap_batch {
   hipStream_t stream = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   void* dtab = nullptr;  // BatchEntry[count], then int first[count + 1]
+  // batches of closure solvers: ClosureInst[count], then int cfirst[count + 1]
+  // (evaluation blocks of the closure sweep per instance, sorted order)
+  bool closure = false;
+  void* ctab = nullptr;
+  std::vector<int> cfirst;
   // launch plan of the current table: sorted instances, sweeps, workgroup prefix
   std::vector<int> order;
   std::vector<int> nsweeps;
@@ -1782,6 +1787,10 @@ namespace starmap {
 namespace detail {
 
 size_t batch_table_bytes(int count) { return align256(size_t(count) * sizeof(BatchEntry)) + size_t(count + 1) * 4; }
+size_t closure_table_bytes(int count) {
+  return align256(size_t(count) * sizeof(ClosureInst)) + size_t(count + 1) * 4;
+}
+int closure_blocks_of(const starmap_solver* s) { return ((s->nx + 1) * (s->ny + 1) + 63) / 64; }
 
 int max_lds_bytes() {
   int dev = 0, max_lds = 64 * 1024;
@@ -1893,6 +1902,7 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
     e.nchunks = int(s->prog[0].chunks.size());
     e.nsweeps = sweeps[ord[r]];
     e.strip = s->tile_strip;
+    e.even_b_delta = s->closure ? int64_t(s->off_prog_b) - int64_t(s->off_prog[0]) : 0;
     first[r] = int(total);
     total += items_of(s);
   }
@@ -1902,6 +1912,36 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
   std::memcpy(buf.data(), tab.data(), tab.size() * sizeof(BatchEntry));
   std::memcpy(buf.data() + align256(size_t(count) * sizeof(BatchEntry)), first.data(), first.size() * 4);
   HIP_TRY(hipMemcpyAsync(b->dtab, buf.data(), buf.size(), hipMemcpyHostToDevice, b->stream));
+  if (b->closure) {
+    // the closure sweep's instances in the same order, with their block prefix
+    std::vector<ClosureInst> ct(ord.size());
+    std::vector<int> cf(ord.size() + 1, 0);
+    int64_t nb = 0;
+    for (size_t r = 0; r < ord.size(); ++r) {
+      starmap_solver* s = b->inst[ord[r]];
+      ClosureInst& c = ct[r];
+      std::memset(&c, 0, sizeof(c));
+      const size_t pb = s->plane_bytes_state();
+      c.u = dptr(s, s->off_state);
+      c.a5 = dptr(s, s->off_state + size_t(closure_plane_a(s)) * pb);
+      c.b5 = dptr(s, s->off_state + size_t(closure_plane_b(s)) * pb);
+      c.decay = dptr(s, s->off_decay);
+      c.tau_full = zero_tau ? 0.0 : s->dt;
+      c.tau_half = zero_tau ? 0.0 : 0.5 * s->dt;
+      c.nsweeps = sweeps[ord[r]];
+      c.G = s->cgeo;
+      c.odd = s->codd;
+      cf[r] = int(nb);
+      nb += closure_blocks_of(s);
+    }
+    if (nb >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "too many closure blocks in one batched sweep");
+    cf[ord.size()] = int(nb);
+    std::vector<char> cb(closure_table_bytes(count), 0);
+    std::memcpy(cb.data(), ct.data(), ct.size() * sizeof(ClosureInst));
+    std::memcpy(cb.data() + align256(size_t(count) * sizeof(ClosureInst)), cf.data(), cf.size() * 4);
+    HIP_TRY(hipMemcpyAsync(b->ctab, cb.data(), cb.size(), hipMemcpyHostToDevice, b->stream));
+    b->cfirst = cf;
+  }
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->order = ord;
   b->nsweeps.resize(ord.size());
@@ -1919,6 +1959,16 @@ int batch_launch(starmap_batch* b, int j0, int j1) {
   for (int j = j0; j < j1; ++j) {
     while (n_active > 0 && b->nsweeps[n_active - 1] <= j) --n_active;
     if (n_active == 0) break;
+    if (b->closure && (j & 1) == 0) {
+      // odd sweep of closure solvers: the network and the odd update in one kernel
+      const ClosureInst* ct = reinterpret_cast<const ClosureInst*>(b->ctab);
+      const int* cf = reinterpret_cast<const int*>(static_cast<char*>(b->ctab) +
+                                                   align256(b->inst.size() * sizeof(ClosureInst)));
+      const starmap_solver* s0 = b->inst[b->order[0]];
+      HIP_TRY(launch_closure_batch(b->storage, ct, cf, n_active, b->cfirst[n_active], j,
+                                   reinterpret_cast<const ClosureNet*>(dptr(s0, s0->off_net)), b->stream));
+      continue;
+    }
     HIP_TRY(launch_sweep_batch(b->storage, b->variant, tab, first, n_active, b->first[n_active], j, b->slots,
                                b->stream));
   }
@@ -1945,7 +1995,12 @@ int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_
     if (v[i]->time_dependent || v[i]->separable)
       return fail(STARMAP_EINVAL, "batched solvers need time-independent data");
     if (v[i]->has_diffusion) return fail(STARMAP_EINVAL, "batched solvers cannot take the D_N diffusion step");
-    if (v[i]->closure) return fail(STARMAP_EINVAL, "closure solvers are not batched");
+    if (v[i]->closure != v[0]->closure)
+      return fail(STARMAP_EINVAL, "a batch holds closure solvers only or none");
+    if (v[i]->closure && !v[i]->closure_loaded)
+      return fail(STARMAP_EINVAL, "batched closure solvers need a loaded network");
+    if (v[i]->closure && v[i]->closure_w != v[0]->closure_w)
+      return fail(STARMAP_EINVAL, "batched closure solvers need one network");
     if (v[i]->storage != v[0]->storage) return fail(STARMAP_EINVAL, "batched solvers need one storage precision");
   }
   {
@@ -1960,6 +2015,8 @@ int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_
   HIP_TRY(hipEventCreate(&b->ev[0]));
   HIP_TRY(hipEventCreate(&b->ev[1]));
   HIP_TRY(hipMalloc(&b->dtab, batch_table_bytes(count)));
+  b->closure = v[0]->closure;
+  if (b->closure) HIP_TRY(hipMalloc(&b->ctab, closure_table_bytes(count)));
   *out = b.release();
   return STARMAP_OK;
 }
@@ -1969,6 +2026,7 @@ void starmap_batch_destroy(starmap_batch* b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graph(b);
   if (b->dtab) (void)hipFree(b->dtab);
+  if (b->ctab) (void)hipFree(b->ctab);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
   if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -2053,6 +2111,16 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
   HIP_TRY(hipEventSynchronize(b->ev[1]));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+  for (size_t r = 0; r < b->order.size(); ++r) {
+    starmap_solver* s = b->inst[b->order[r]];
+    if (b->closure) {
+      // (nsweeps + 1) / 2 odd sweeps each moved the order-5 moments once
+      s->c5_flip = ((b->nsweeps[r] + 1) / 2) & 1;
+      rc = closure_settle(s);
+      if (rc) return rc;
+      HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+  }
   for (auto* s : b->inst) {
     s->steps_done = s->steps_total;
     s->t = double(s->steps_done) * s->dt;
@@ -2104,12 +2172,15 @@ int starmap_batch_autotune(starmap_batch* b, int32_t sweeps) {
       if (sweep_lds_bytes(v, slots, b->storage) > size_t(max_lds)) continue;
       int rc = batch_prepare(b, v, w);
       if (rc) return rc;
-      // tau = 0 leaves every value unchanged; three sweeps: odd, even, odd
+      // tau = 0 leaves every value unchanged; three sweeps: odd, even, odd.
+      // A closure batch times the first pair (odd sweep 0 copies the order-5
+      // moments into the closure planes, even sweep 1 reads them there)
+      const int j0 = b->closure ? 0 : 1;
       rc = batch_table(b, std::vector<int>(count, 3), true);
-      if (!rc) rc = batch_launch(b, 1, 3);
+      if (!rc) rc = batch_launch(b, j0, j0 + 2);
       if (rc) return rc;
       HIP_TRY(hipEventRecord(b->ev[0], b->stream));
-      for (int i = 0; i < sweeps && !rc; ++i) rc = batch_launch(b, 1, 3);
+      for (int i = 0; i < sweeps && !rc; ++i) rc = batch_launch(b, j0, j0 + 2);
       if (rc) return rc;
       HIP_TRY(hipEventRecord(b->ev[1], b->stream));
       HIP_TRY(hipEventSynchronize(b->ev[1]));

@@ -287,6 +287,7 @@ int starmap_closure_load(starmap_solver* s, const float* w, size_t count) {
     }
   }
   if (q != CLOSURE_ODD_ROWS) return fail(STARMAP_EINVAL, "closure: unexpected number of odd moments");
+  s->closure_w.assign(w, w + count);
   s->closure_loaded = true;
   return STARMAP_OK;
 }

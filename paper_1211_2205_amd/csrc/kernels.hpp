@@ -61,6 +61,9 @@ struct BatchEntry {
   int zero_off[2];
   int nsweeps;  // sweeps still to run: 2 n + 1 for n steps
   int strip;    // tile rows per strip of the tile order
+  // closure solvers: bytes from the even sweep's program to the one that reads
+  // the order-5 moments from the closure planes (0: none)
+  int64_t even_b_delta;
 };
 
 // Opts the kernels of a variant in to the LDS it needs (outside any stream

@@ -336,21 +336,29 @@ constexpr int LDW = CLOSURE_IN + 8;  // LDS row of one point's activations (bf16
 template <typename T, typename C>
 __device__ __forceinline__ C closure_odd_update(const T* __restrict__ U, const ClosureOddRow& r, const ClosureGeo& G,
                                                 int X, int Y, C u, C g, C c, C E, C tau) {
-  const int64_t ps = G.plane_stride;
+  // plane bases are wave-uniform; the lane's offsets are 32-bit byte offsets
+  // within a plane (planes stay below 2^31 bytes), so every load takes a
+  // scalar base and one offset register
+  const uint64_t ps = uint64_t(G.plane_stride);
+  constexpr uint32_t TS = sizeof(T);
+  const char* base = reinterpret_cast<const char*>(U);
+  auto val = [&](int k, uint32_t off) {
+    return to_c(*reinterpret_cast<const T*>(base + uint64_t(uint32_t(k)) * ps * TS + off));
+  };
+  const uint32_t row = uint32_t(Y) * uint32_t(G.pitch);
   C W = C(0);
   for (int t = 0; t < r.nx; ++t) {
-    const T* up = U + int64_t(r.xk[t]) * ps + int64_t(Y) * G.pitch;
     const int lo = r.xcell[t] ? map_axis(X - 1, G.nx, G.px, 1) : map_axis(X, G.nx, G.px, 0);
     const int hi = r.xcell[t] ? map_axis(X, G.nx, G.px, 1) : map_axis(X + 1, G.nx, G.px, 0);
-    W = couple(W, C(r.xc[t]), to_c(up[hi]), to_c(up[lo]));
+    W = couple(W, C(r.xc[t]), val(r.xk[t], (row + uint32_t(hi)) * TS), val(r.xk[t], (row + uint32_t(lo)) * TS));
   }
   for (int t = 0; t < r.ny; ++t) {
-    const T* up = U + int64_t(r.yk[t]) * ps + X;
     const int lo = r.ycell[t] ? map_axis(Y - 1, G.ny, G.py, 1) : map_axis(Y, G.ny, G.py, 0);
     const int hi = r.ycell[t] ? map_axis(Y, G.ny, G.py, 1) : map_axis(Y + 1, G.ny, G.py, 0);
-    W = couple(W, C(r.yc[t]), to_c(up[int64_t(hi) * G.pitch]), to_c(up[int64_t(lo) * G.pitch]));
+    W = couple(W, C(r.yc[t]), val(r.yk[t], (uint32_t(hi) * uint32_t(G.pitch) + uint32_t(X)) * TS),
+               val(r.yk[t], (uint32_t(lo) * uint32_t(G.pitch) + uint32_t(X)) * TS));
   }
-  if (r.src >= 0) W += to_c(U[int64_t(r.src) * ps + int64_t(Y) * G.pitch + X]);
+  if (r.src >= 0) W += val(r.src, (row + uint32_t(X)) * TS);
   if (r.o >= 0) W += g;
   return sub_step(u, W, c, E, tau);
 }
@@ -362,12 +370,22 @@ __device__ __forceinline__ C closure_odd_update(const T* __restrict__ U, const C
 // that lies on its grid), the order-5 moments read from in5 and written to
 // out5 (out of place, so every workgroup's stencils see the state of the
 // start of the sweep), orders 1 and 3 in place (nothing else reads them).
-template <typename T, bool FUSED>
-__global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U, const T* __restrict__ in5,
-                                                            T* __restrict__ out5,
-                                                            const typename ComputeOf<T>::type* __restrict__ decay,
-                                                            const ClosureGeo G, const ClosureNet* __restrict__ net,
-                                                            const ClosureOdd odd) {
+//
+// BATCH = true (with FUSED): odd sweep number j of a batched run of closure
+// solvers sharing one network; instance i (of the n_active still running,
+// sorted by their sweep counts) owns the evaluation blocks
+// [bfirst[i], bfirst[i + 1]) and brings its own state, geometry and odd rows
+// (insts[i]); the arguments U .. odd are unused.
+template <typename T, bool FUSED, bool BATCH>
+__global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U0, const T* __restrict__ in5_0,
+                                                            T* __restrict__ out5_0,
+                                                            const typename ComputeOf<T>::type* __restrict__ decay0,
+                                                            const ClosureGeo G0, const ClosureNet* __restrict__ net,
+                                                            const ClosureOdd odd0,
+                                                            const ClosureInst* __restrict__ insts,
+                                                            const int* __restrict__ bfirst, const int n_active,
+                                                            const int jsweep) {
+  static_assert(FUSED || !BATCH, "batched runs use the fused sweep");
   using C = typename ComputeOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* Xa = reinterpret_cast<uint16_t*>(smem);  // [64][LDW] inputs, then layer-2 activations
@@ -382,7 +400,9 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
 
   // the output geometry, indexed per lane below, from LDS (indexing the
   // kernel argument per lane would turn every access into a dependent load)
-  if (tid < 5 * 8) {
+  const ClosureGeo& Gk = G0;
+  if (!FUSED && tid < 5 * 8) {
+    const ClosureGeo& G = Gk;
     const int f = tid >> 3, o = tid & 7;
     int v = 0;
     if (o < CLOSURE_OUT)
@@ -409,9 +429,33 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
 #pragma unroll
   for (int r = 0; r < 4; ++r) b3[r] = net->b3[4 * (lane >> 4) + r];
 
-  const int NXE = G.nx + 1, total = NXE * (G.ny + 1);
-  const int nblk = (total + CB - 1) / CB;
-  for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  const int nblk = BATCH ? bfirst[n_active] : ((G0.nx + 1) * (G0.ny + 1) + CB - 1) / CB;
+  for (int gblk = blockIdx.x; gblk < nblk; gblk += gridDim.x) {
+    // this block's instance (batched runs) and its data
+    int inst = 0;
+    if constexpr (BATCH) {
+      int lo = 0, hi = n_active - 1;  // last instance with bfirst[i] <= gblk
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bfirst[mid] <= gblk) lo = mid; else hi = mid - 1;
+      }
+      inst = lo;
+    }
+    const int blk = BATCH ? gblk - bfirst[inst] : gblk;
+    const ClosureGeo& G = BATCH ? insts[inst].G : G0;
+    const ClosureOdd& odd = BATCH ? insts[inst].odd : odd0;
+    T* const U = BATCH ? static_cast<T*>(insts[inst].u) : U0;
+    const C* const decay = BATCH ? static_cast<const C*>(insts[inst].decay) : decay0;
+    // the order-5 moments move between the state planes and the closure
+    // planes at every odd sweep: odd sweep j of a batched run reads them
+    // where j / 2 earlier odd sweeps left them
+    const bool flip = BATCH && ((jsweep >> 1) & 1);
+    const T* const in5 = BATCH ? static_cast<const T*>(flip ? insts[inst].b5 : insts[inst].a5) : in5_0;
+    T* const out5 = BATCH ? static_cast<T*>(flip ? insts[inst].a5 : insts[inst].b5) : out5_0;
+    const C tau = BATCH ? C((jsweep == 0 || jsweep == insts[inst].nsweeps - 1) ? insts[inst].tau_half
+                                                                             : insts[inst].tau_full)
+                        : C(odd0.tau);
+    const int NXE = G.nx + 1, total = NXE * (G.ny + 1);
     // 1. inputs: wave w gathers moments w, w + 4, w + 8 of point lane
     const int pt = blk * CB + lane;
     const bool live = pt < total;
@@ -577,17 +621,17 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
         const int64_t off = int64_t(Y) * G.pitch + X;
         if (nd && r.dk != dk21) {
           c21 = decay[int64_t(r.dk) * G.plane_stride + off];
-          e21 = expm1div(-c21 * C(odd.tau));
+          e21 = expm1div(-c21 * tau);
           dk21 = r.dk;
         } else if (!nd && r.dk != dk12) {
           c12 = decay[int64_t(r.dk) * G.plane_stride + off];
-          e12 = expm1div(-c12 * C(odd.tau));
+          e12 = expm1div(-c12 * tau);
           dk12 = r.dk;
         }
         const T* src = r.o >= 0 ? in5 + int64_t(r.o) * G.plane_stride : U + int64_t(r.k) * G.plane_stride;
         const C u = to_c(src[off]);
         const C g = r.o >= 0 ? gsh[r.o * CB + lane] : C(0);
-        const C v = closure_odd_update(U, r, G, X, Y, u, g, nd ? c21 : c12, nd ? e21 : e12, C(odd.tau));
+        const C v = closure_odd_update(U, r, G, X, Y, u, g, nd ? c21 : c12, nd ? e21 : e12, tau);
         T* dst = r.o >= 0 ? out5 + int64_t(r.o) * G.plane_stride : U + int64_t(r.k) * G.plane_stride;
         dst[off] = from_c<T>(v);
       }
@@ -662,26 +706,26 @@ size_t closure_infer_lds_bytes() {
 }
 
 namespace {
-template <typename T, bool FUSED>
+template <typename T, bool FUSED, bool BATCH>
 hipError_t launch_infer_t(void* U, const void* in5, void* out5, const void* decay, const ClosureGeo& G,
-                          const ClosureNet* net, const ClosureOdd& odd, int blocks, hipStream_t stream) {
+                          const ClosureNet* net, const ClosureOdd& odd, const ClosureInst* insts, const int* bfirst,
+                          int n_active, int j, int blocks, hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   static bool attr = false;
   const size_t lds = closure_infer_lds_bytes();
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&closure_infer_kernel<T, FUSED>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&closure_infer_kernel<T, FUSED, BATCH>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((closure_infer_kernel<T, FUSED>), dim3(blocks), dim3(256), lds, stream, static_cast<T*>(U),
-                     static_cast<const T*>(in5), static_cast<T*>(out5), static_cast<const C*>(decay), G, net, odd);
+  hipLaunchKernelGGL((closure_infer_kernel<T, FUSED, BATCH>), dim3(blocks), dim3(256), lds, stream,
+                     static_cast<T*>(U), static_cast<const T*>(in5), static_cast<T*>(out5),
+                     static_cast<const C*>(decay), G, net, odd, insts, bfirst, n_active, j);
   return hipGetLastError();
 }
 
-// a few workgroups per compute unit, each looping over blocks of points with
-// the weights loaded once
-int infer_blocks(const ClosureGeo& G) {
+int device_cus() {
   static int cus = 0;
   if (!cus) {
     int dev = 0;
@@ -689,9 +733,15 @@ int infer_blocks(const ClosureGeo& G) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
       cus = 256;
   }
+  return cus;
+}
+
+// a few workgroups per compute unit, each looping over blocks of points with
+// the weights loaded once
+int infer_blocks(const ClosureGeo& G) {
   const int total = (G.nx + 1) * (G.ny + 1);
   const int nblk = (total + CB - 1) / CB;
-  return std::min(nblk, 3 * cus);
+  return std::min(nblk, 3 * device_cus());
 }
 }  // namespace
 
@@ -703,18 +753,18 @@ hipError_t launch_closure_infer(int storage, void* U, const void* decay, const C
   switch (storage) {
     case STORE_FP64: {
       double* u = static_cast<double*>(U);
-      return launch_infer_t<double, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net, none,
-                                           blocks, stream);
+      return launch_infer_t<double, false, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net,
+                                                  none, nullptr, nullptr, 0, 0, blocks, stream);
     }
     case STORE_FP32: {
       float* u = static_cast<float*>(U);
-      return launch_infer_t<float, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net, none,
-                                          blocks, stream);
+      return launch_infer_t<float, false, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net,
+                                                 none, nullptr, nullptr, 0, 0, blocks, stream);
     }
     case STORE_BF16: {
       bf16* u = static_cast<bf16*>(U);
-      return launch_infer_t<bf16, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net, none,
-                                         blocks, stream);
+      return launch_infer_t<bf16, false, false>(U, u + int64_t(G.k[5]) * G.plane_stride, nullptr, decay, G, net,
+                                                none, nullptr, nullptr, 0, 0, blocks, stream);
     }
   }
   return hipErrorInvalidValue;
@@ -725,9 +775,35 @@ hipError_t launch_closure_sweep(int storage, void* U, const void* in5, void* out
                                 hipStream_t stream) {
   const int blocks = infer_blocks(G);
   switch (storage) {
-    case STORE_FP64: return launch_infer_t<double, true>(U, in5, out5, decay, G, net, odd, blocks, stream);
-    case STORE_FP32: return launch_infer_t<float, true>(U, in5, out5, decay, G, net, odd, blocks, stream);
-    case STORE_BF16: return launch_infer_t<bf16, true>(U, in5, out5, decay, G, net, odd, blocks, stream);
+    case STORE_FP64:
+      return launch_infer_t<double, true, false>(U, in5, out5, decay, G, net, odd, nullptr, nullptr, 0, 0, blocks,
+                                                 stream);
+    case STORE_FP32:
+      return launch_infer_t<float, true, false>(U, in5, out5, decay, G, net, odd, nullptr, nullptr, 0, 0, blocks,
+                                                stream);
+    case STORE_BF16:
+      return launch_infer_t<bf16, true, false>(U, in5, out5, decay, G, net, odd, nullptr, nullptr, 0, 0, blocks,
+                                               stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_closure_batch(int storage, const ClosureInst* insts, const int* bfirst, int n_active, int blocks,
+                                int j, const ClosureNet* net, hipStream_t stream) {
+  if (n_active < 1 || blocks < 1) return hipErrorInvalidValue;
+  const int grid = std::min(blocks, 3 * device_cus());
+  const ClosureGeo G{};
+  const ClosureOdd odd{};
+  switch (storage) {
+    case STORE_FP64:
+      return launch_infer_t<double, true, true>(nullptr, nullptr, nullptr, nullptr, G, net, odd, insts, bfirst,
+                                                n_active, j, grid, stream);
+    case STORE_FP32:
+      return launch_infer_t<float, true, true>(nullptr, nullptr, nullptr, nullptr, G, net, odd, insts, bfirst,
+                                               n_active, j, grid, stream);
+    case STORE_BF16:
+      return launch_infer_t<bf16, true, true>(nullptr, nullptr, nullptr, nullptr, G, net, odd, insts, bfirst,
+                                              n_active, j, grid, stream);
   }
   return hipErrorInvalidValue;
 }

@@ -71,6 +71,21 @@ struct ClosureOdd {
   double tau;
 };
 
+// One instance of a batched run of closure solvers (device table): its state
+// planes, the two homes of its order-5 moments (state planes a5, closure
+// planes b5), decay planes, sub-step lengths, sweep count, geometry and odd
+// rows.
+struct ClosureInst {
+  void* u;
+  void* a5;
+  void* b5;
+  const void* decay;
+  double tau_full, tau_half;
+  int nsweeps, pad;
+  ClosureGeo G;
+  ClosureOdd odd;
+};
+
 struct GemmArgs {
   const float* A;
   int64_t sam, sak;
@@ -114,6 +129,11 @@ hipError_t launch_closure_infer(int storage, void* U, const void* decay, const C
 hipError_t launch_closure_sweep(int storage, void* U, const void* in5, void* out5, const void* decay,
                                 const ClosureGeo& G, const ClosureNet* net, const ClosureOdd& odd,
                                 hipStream_t stream);
+// Odd sweep j of a batched run of closure solvers (FUSED kernel, BATCH mode):
+// the first n_active instances of insts, evaluation blocks numbered from
+// bfirst[i]; one network for all.
+hipError_t launch_closure_batch(int storage, const ClosureInst* insts, const int* bfirst, int n_active, int blocks,
+                                int j, const ClosureNet* net, hipStream_t stream);
 size_t closure_infer_lds_bytes();
 
 }  // namespace starmap

@@ -133,14 +133,16 @@ struct starmap_solver {
   // learned closure (order 5): network region, geometry, weights loaded
   bool closure = false;
   bool closure_loaded = false;
-  // fused closure sweep (default): the order-5 moments alternate between their
-  // state planes (A) and the closure planes (B); c5_flip = 1 while the current
-  // values sit in B (only between the odd sweeps of one advance call); the
-  // even sweep then reads them through a second program (off_prog_b)
-  bool closure_fused = true;
+  // fused closure sweep (starmap_closure_set_fused; batches always use it):
+  // the order-5 moments alternate between their state planes (A) and the
+  // closure planes (B); c5_flip = 1 while the current values sit in B (only
+  // between the odd sweeps of one advance call); the even sweep then reads
+  // them through a second program (off_prog_b)
+  bool closure_fused = false;
   int c5_flip = 0;
   size_t off_prog_b = 0;
   starmap::ClosureOdd codd{};
+  std::vector<float> closure_w;  // the loaded parameter blob (batches need one network)
   size_t off_net = 0;
   starmap::ClosureGeo cgeo{};
   void* sample_buf = nullptr;  // device copy of training-sample points

@@ -65,6 +65,26 @@ __device__ __forceinline__ bf16 load_stream(const bf16* p) {
   return bf16{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
 }
 
+// Two x-adjacent bfloat16 values as one 32-bit access (4-byte aligned).
+__device__ __forceinline__ void load_pair(const bf16* p, bf16& lo, bf16& hi) {
+  const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+  lo = bf16{uint16_t(w & 0xFFFFu)};
+  hi = bf16{uint16_t(w >> 16)};
+}
+__device__ __forceinline__ uint32_t load_pair_stream(const bf16* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+}
+__device__ __forceinline__ void store_pair_stream(bf16* p, bf16 lo, bf16 hi) {
+  __builtin_nontemporal_store(uint32_t(lo.bits) | (uint32_t(hi.bits) << 16), reinterpret_cast<uint32_t*>(p));
+}
+// (never called for the other storage types)
+template <typename T>
+__device__ __forceinline__ void load_pair(const T*, T&, T&) {}
+template <typename T>
+__device__ __forceinline__ uint32_t load_pair_stream(const T*) { return 0; }
+template <typename T>
+__device__ __forceinline__ void store_pair_stream(T*, T, T) {}
+
 // s_waitcnt immediate for vmcnt(0) with the other counters left alone
 // (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
@@ -93,6 +113,11 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   constexpr int RB = CAP - 2;  // an m range of width w has w rows and w + 2 staged planes per order
   constexpr int LB = sizeof(T) >= 8 ? 8 : 16;  // planes per batch of the synchronous staging
   constexpr int EPT = PPT + 1;                 // staged points per thread and plane: interior + halo
+  // BF16 on tiles of 512 points: each thread owns two x-adjacent points, and
+  // on tiles away from the right edge of the grid (where no staging index
+  // is clamped or wrapped) the pair moves as one 32-bit access: 2-byte
+  // accesses would move half the bytes per instruction
+  constexpr bool PAIR = sizeof(T) == 2 && PPT == 2;
 
   const int tid = threadIdx.x;
   const int tile = lb / a.nchunks;
@@ -102,6 +127,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   const int x0 = txy.x * TX;
   const int y0 = txy.y * TY;
   const int grp = 0;
+  const bool pfast = PAIR && x0 + TX <= a.nx;  // uniform: every interior index maps to itself
 
   // Staging of one input plane into its (TX+1) x (TY+1) LDS tile.  The tile
   // holds global points (x0 - ox + lx, y0 - oy + ly), with ox (oy) = 1 for an
@@ -120,7 +146,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   bool sv[EPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int e = tid + p * 256;
+    const int e = PAIR ? 2 * tid + p : tid + p * 256;
     const int tx = e % TX, ty = e / TX;
     const int xn = map_axis(x0 + tx, a.nx, a.px, 0), xc = map_axis(x0 + tx, a.nx, a.px, 1);
     const int yn = map_axis(y0 + ty, a.ny, a.py, 0), yc = map_axis(y0 + ty, a.ny, a.py, 1);
@@ -171,7 +197,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     const int vx1 = a.parity ? nxc : nxn, vy1 = a.parity ? nyn : nyn;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      const int e = tid + p * 256;
+      const int e = PAIR ? 2 * tid + p : tid + p * 256;
       const int tx = e % TX, ty = e / TX;
       const int X = x0 + tx, Y = y0 + ty;
       pos[p] = ty * LW + tx;
@@ -181,20 +207,26 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     }
   }
 
+  // the staged points of one input plane (load record ld) into registers
+  auto load_window = [&](T (&v)[EPT], const int4 ld) {
+    const T* src = plane_at(U, ld.x, a.ps);
+    const uint32_t mx = 0u - uint32_t(ld.z), my = 0u - uint32_t(ld.w);
+    if (PAIR && pfast) {
+      load_pair(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)), v[0], v[1]);
+      v[EPT - 1] = *at(src, sb[EPT - 1] + (sx[EPT - 1] & mx) + (sy[EPT - 1] & my));
+    } else {
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) v[q] = *at(src, sb[q] + (sx[q] & mx) + (sy[q] & my));
+    }
+  };
+
   // synchronous staging of planes [b0, b1) of a load list into LDS
   auto stage_sync = [&](int first, int b0, int b1) {
     for (int bb = b0; bb < b1; bb += LB) {
       T v[LB][EPT];
 #pragma unroll
-      for (int b = 0; b < LB; ++b) {
-        if (bb + b < b1) {
-          const int4 ld = rec4(loads, first + bb + b);
-          const T* src = plane_at(U, ld.x, a.ps);
-#pragma unroll
-          for (int q = 0; q < EPT; ++q)
-            v[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
-        }
-      }
+      for (int b = 0; b < LB; ++b)
+        if (bb + b < b1) load_window(v[b], rec4(loads, first + bb + b));
 #pragma unroll
       for (int b = 0; b < LB; ++b) {
         if (bb + b < b1) {
@@ -216,8 +248,21 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         cptr<int> rec = cat(rows, uint32_t(r) * 64u);
         const T* up = plane_at(U, rec[0], a.ps);
         const bool s1 = rec[1] != 0;
+        bool done = false;
+        if constexpr (PAIR) {
+          if (pfast) {  // both points of the pair lie inside the output grid along x
+            uint32_t w = 0;
+            if (s1 ? val1[0] : val0[0]) w = load_pair_stream(at(up, goff[0] * TS));
+            uv[i][0] = to_c(bf16{uint16_t(w & 0xFFFFu)});
+            uv[i][PPT - 1] = to_c(bf16{uint16_t(w >> 16)});
+            done = true;
+          }
+        }
+        if (!done) {
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(load_stream(at(up, goff[p] * TS))) : C(0);
+          for (int p = 0; p < PPT; ++p)
+            uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(load_stream(at(up, goff[p] * TS))) : C(0);
+        }
       }
     }
   };
@@ -292,15 +337,8 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     // 1. the next window into registers (every thread loads its own elements)
     T stg[MAXP][EPT];
 #pragma unroll
-    for (int b = 0; b < MAXP; ++b) {
-      if (b < nl) {
-        const int4 ld = rec4(loads, nxt.x + b);
-        const T* src = plane_at(U, ld.x, a.ps);
-#pragma unroll
-        for (int q = 0; q < EPT; ++q)
-          stg[b][q] = *at(src, sb[q] + (sx[q] & (0u - uint32_t(ld.z))) + (sy[q] & (0u - uint32_t(ld.w))));
-      }
-    }
+    for (int b = 0; b < MAXP; ++b)
+      if (b < nl) load_window(stg[b], rec4(loads, nxt.x + b));
     // 2. the first output rows of the next order
     C ub[RB][PPT];
     if (has_next) {
@@ -321,6 +359,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
           cptr<C> cf = cat(rcoef, uint32_t(r) * uint32_t(8 * sizeof(C)));
           const int k = rec[0], gslot = rec[1], so = rec[3];
           T* up = plane_at(U, k, a.ps);
+          T nv[PPT];
 #pragma unroll
           for (int p = 0; p < PPT; ++p) {
             C W = C(0);
@@ -336,13 +375,12 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
             }
     // the source, staged in LDS, joins the residual
             if (so >= 0) W += to_c(L[so + pos[p]]);
-            if (gslot ? val1[p] : val0[p]) {
-              const C c = gslot ? c1[p] : c0[p];
-              const C E = gslot ? e1[p] : e0[p];
-              const C u = ua[i][p];
-              store_stream(at(up, goff[p] * TS), from_c<T>(sub_step(u, W, c, E, a.tau)));
-            }
+            const C c = gslot ? c1[p] : c0[p];
+            const C E = gslot ? e1[p] : e0[p];
+            nv[p] = from_c<T>(sub_step(ua[i][p], W, c, E, a.tau));
+            if (!(PAIR && pfast) && (gslot ? val1[p] : val0[p])) store_stream(at(up, goff[p] * TS), nv[p]);
           }
+          if (PAIR && pfast && (gslot ? val1[0] : val0[0])) store_pair_stream(at(up, goff[0] * TS), nv[0], nv[PPT - 1]);
         }
       }
     }
@@ -410,8 +448,10 @@ struct BatchEntryG {
   int zero_off[2];
   int nsweeps;
   int strip;
+  int64_t even_b_delta;
 };
 static_assert(sizeof(BatchEntryG) == sizeof(BatchEntry), "device view of BatchEntry");
+static_assert(offsetof(BatchEntryG, even_b_delta) == offsetof(BatchEntry, even_b_delta), "device view of BatchEntry");
 static_assert(offsetof(BatchEntryG, plane_stride) == offsetof(BatchEntry, plane_stride), "device view of BatchEntry");
 static_assert(offsetof(BatchEntryG, nsweeps) == offsetof(BatchEntry, nsweeps), "device view of BatchEntry");
 
@@ -428,6 +468,9 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
   }
   const BatchEntryG& e = reinterpret_cast<const BatchEntryG*>(table)[lo];
   const int par = (j & 1) ? 0 : 1;
+  // closure solvers: before even sweep j, (j + 1) / 2 odd sweeps have moved
+  // the order-5 moments; an odd count leaves them in the closure planes
+  const int64_t bd = (par == 0 && (((j + 1) >> 1) & 1)) ? e.even_b_delta : 0;
   SweepScalars<C> a;
   a.ps = uint32_t(e.plane_stride);
   a.pitch = e.pitch;
@@ -442,9 +485,12 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
   a.parity = par;
   a.strip = e.strip;
   a.tau = C((j == 0 || j == e.nsweeps - 1) ? e.tau_half : e.tau_full);
-  sweep_tile<T, TX, TY, CAP>((T*)(gptr<T>)e.u, (const C*)(gptr<const C>)e.decay, (cptr<int>)e.chunks[par],
-                             (cptr<int>)e.orders[par], (cptr<int>)e.loads[par], (cptr<int>)e.rows[par],
-                             (cptr<C>)e.rcoef[par], a, item - first[lo]);
+  sweep_tile<T, TX, TY, CAP>((T*)(gptr<T>)e.u, (const C*)(gptr<const C>)e.decay,
+                             (cptr<int>)((gptr<const char>)e.chunks[par] + bd),
+                             (cptr<int>)((gptr<const char>)e.orders[par] + bd),
+                             (cptr<int>)((gptr<const char>)e.loads[par] + bd),
+                             (cptr<int>)((gptr<const char>)e.rows[par] + bd),
+                             (cptr<C>)((gptr<const char>)e.rcoef[par] + bd), a, item - first[lo]);
 }
 
 // ------------------------------------------------------------ variants

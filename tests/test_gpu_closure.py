@@ -233,8 +233,8 @@ def test_trained_closure_gains_over_plain_p5():
         ec = oc.r00_error(runs["p5c"], runs["ref"])
         print(f"held-out {k}: P_5 error {e5:.3e}, P_5 + closure {ec:.3e}", flush=True)
         gains.append(e5 / ec)
-    # per-instance gains on the 64-instance evaluation range from 1.001 to 2.6
-    assert min(gains) > 1.0 and float(np.mean(gains)) > 1.3, gains
+    # per-instance gains on the 64-instance evaluation range from 2.4 to 5.2
+    assert min(gains) > 2.0 and float(np.mean(gains)) > 2.5, gains
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -286,3 +286,57 @@ def test_fused_closure_bf16_storage_close_to_separate():
         outs.append(s.moments())
         s.close()
     assert rel_l2(outs[0], outs[1]) < 2e-2
+
+
+def test_batched_closure_solvers_equal_single_runs():
+    """A batch of closure solvers (one network; ragged grids and every boundary
+    mix; uneven step counts): each instance ends bitwise equal to its own
+    single-solver run, with graphs and without, after the batch autotuner."""
+    p = mlp.flatten(_params(13, out_scale=0.2))
+    cases = [((24, 20), (wl.BC_EXTRAPOLATION, wl.BC_EXTRAPOLATION), 41),
+             ((33, 16), (wl.BC_PERIODIC, wl.BC_EXTRAPOLATION), 42),
+             ((20, 41), (wl.BC_EXTRAPOLATION, wl.BC_PERIODIC), 43),
+             ((48, 48), (wl.BC_PERIODIC, wl.BC_PERIODIC), 44)]
+    for precision in ("fp64", "fp32"):
+        probs = [_state_problem(5, n, bc, seed, precision=precision) for n, bc, seed in cases]
+        singles = []
+        for prob in probs:
+            s = pa.Solver.from_problem(prob, precision=precision, closure="learned")
+            s.load_closure(p)
+            s.run()
+            singles.append(s.moments())
+            s.close()
+        for use_graph in (True, False):
+            solvers = []
+            for prob in probs:
+                s = pa.Solver.from_problem(prob, precision=precision, closure="learned")
+                s.load_closure(p)
+                solvers.append(s)
+            b = pa.Batch(solvers)
+            b.autotune(1)
+            b.run(use_graph=use_graph)
+            for k, (s, ref) in enumerate(zip(solvers, singles)):
+                for x, y in zip(s.moments(), ref):
+                    np.testing.assert_array_equal(x, y, err_msg=f"{precision} instance {k} graph {use_graph}")
+            b.close()
+            for s in solvers:
+                s.close()
+        print(f"batched closure {precision}: {len(probs)} instances identical to single runs", flush=True)
+
+
+def test_batched_closure_rules():
+    p = mlp.flatten(_params(14, out_scale=0.2))
+    q = mlp.flatten(_params(15, out_scale=0.2))
+    prob = _state_problem(5, (16, 16), (wl.BC_EXTRAPOLATION, wl.BC_EXTRAPOLATION), 45)
+    a = pa.Solver.from_problem(prob, closure="learned")
+    a.load_closure(p)
+    c = pa.Solver.from_problem(prob, closure="learned")
+    c.load_closure(q)
+    plain = pa.Solver.from_problem(prob)
+    with pytest.raises(pa.StarmapError):
+        pa.Batch([a, plain])   # closure and plain solvers together
+    with pytest.raises(pa.StarmapError):
+        pa.Batch([a, c])       # two networks
+    d = pa.Solver.from_problem(prob, closure="learned")
+    with pytest.raises(pa.StarmapError):
+        pa.Batch([d])          # no network loaded

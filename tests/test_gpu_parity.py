@@ -141,6 +141,39 @@ def test_fp32_tile_variants_are_bitwise_identical(case, monkeypatch):
     assert_parity(ref, o.u, FP32_TOL, f"{case} FP32 vs oracle:")
 
 
+@pytest.mark.parametrize("bc", [("extrapolation", "extrapolation"), ("periodic", "periodic"),
+                                ("periodic", "extrapolation")])
+def test_bf16_tile_variants_are_bitwise_identical(bc, monkeypatch):
+    """BF16 storage: tiles of 512 points move x-adjacent pairs as one 32-bit
+    access away from the grid's right edge (and single values at the edge);
+    tiles of 256 points move single values.  Every variant gives the same
+    bits, on a grid (150 x 77) that has both kinds of 512-point tiles."""
+    prob = wl.random_medium(35, 9, 150, t_final=0.2, precision="bf16")
+    prob.n = (150, 77)
+    prob.bc = bc
+    ref, tried = None, []
+    for width in (4, 8):
+        monkeypatch.setenv("STARMAP_CHUNK_WIDTH", str(width))
+        for v in range(pa.variant_count()):
+            s = pa.Solver.from_problem(prob, precision="bf16")
+            s.bind_torch()
+            try:
+                s.set_variant(v)
+            except pa.StarmapError:
+                continue
+            tried.append((v, width))
+            s.advance(6)
+            out = s.moments()
+            if ref is None:
+                ref = out
+            else:
+                for a, b in zip(out, ref):
+                    assert np.array_equal(a, b), f"variant {v} width {width} differs"
+    assert len(tried) >= 8
+    o = run_oracle(prob, nsteps=6)
+    assert_parity(ref, o.u, 2e-2, f"BF16 {bc} vs oracle:", moment_tol=1e-1, elem_tol=5e-2)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
 def test_c2_checkerboard_full_run(precision, tol):
     prob = wl.config("c2")
