@@ -70,32 +70,40 @@ def _traffic(rec, variant, width, n_odd, n_even, alg_odd, alg_even):
     return (n_odd * odd["hbm_bytes_per_launch"] + n_even * even["hbm_bytes_per_launch"]) / n
 
 
-def cpu_baseline(prob, rows):
+def cpu_baseline(prob, rows, steps=1, rows_single=200):
     """Oracle (FP64, plain C + OpenMP) on a band of `rows` grid rows of the same
-    workload for one full step, on all host threads, then on one thread (the
-    same band: the oracle is memory-bound, a smaller band would sit in cache)."""
+    workload (all of them: the workload itself) for `steps` full steps on all
+    host threads, then one step on one thread on a band of `rows_single` rows
+    (the oracle is memory-bound, a smaller band would sit in cache)."""
     import workloads as wl
     from oracle import scheme
     from oracle.scheme import OracleSolver
     h = (prob.ax[1] - prob.ax[0]) / prob.n[0]
 
-    def run(r):
-        band = wl.line_source(N=prob.N, n=prob.n[0], s=0.01, precision="fp64")
-        band.n = (prob.n[0], r)
-        band.ax = (prob.ax[0], prob.ax[1], -r * h / 2, r * h / 2)
+    def run(r, k):
+        if r >= prob.n[1]:
+            band = wl.line_source(N=prob.N, n=prob.n[0], s=0.01, precision="fp64")
+            what = f"the full {prob.n[0]} x {prob.n[1]} grid"
+        else:
+            band = wl.line_source(N=prob.N, n=prob.n[0], s=0.01, precision="fp64")
+            band.n = (prob.n[0], r)
+            band.ax = (prob.ax[0], prob.ax[1], -r * h / 2, r * h / 2)
+            what = f"a {prob.n[0]} x {r} band"
         o = OracleSolver(band)
         o.evaluate_materials(0.0)
         t0 = time.perf_counter()
-        o.step()
+        for _ in range(k):
+            o.step()
         t1 = time.perf_counter()
-        updates = prob.n[0] * r * o.nmom
-        return updates / (t1 - t0), (f"one full step (4 half-steps) of P_{prob.N} on a {prob.n[0]} x {r} band "
+        updates = band.n[0] * band.n[1] * o.nmom * k
+        del o
+        return updates / (t1 - t0), (f"{k} full step(s) (4 half-steps each) of P_{prob.N} on {what} "
                                      f"({updates:.3e} cell-moment updates, {t1 - t0:.1f} s, FP64)")
 
     all_threads = scheme.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0)))
-    v, sample = run(rows)
+    v, sample = run(rows, steps)
     scheme.set_threads(1)
-    v1, sample1 = run(rows)
+    v1, sample1 = run(rows_single, 1)
     scheme.set_threads(all_threads)
     model = None
     try:
@@ -123,12 +131,11 @@ def batch_leg(count, precision):
     t0 = time.perf_counter()
     rec = b.run()
     wall = time.perf_counter() - t0
-    v, w = b.variant()
     achieved = rec["bytes"] / (rec["ms"] * 1e-3) / 1e9
     out = {"workload": f"random_media_batch_{count}_{precision}", "instances": count,
            "value": rec["updates"] / wall, "unit": "cell-moment updates/s",
            "device_ms": rec["ms"], "wall_ms": wall * 1e3, "launches": rec["launches"],
-           "updates": rec["updates"], "tile_variant": v, "m_range_width": w,
+           "updates": rec["updates"], "groups": b.groups(),
            "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS}
     b.close()
     for x in solvers:
@@ -283,6 +290,17 @@ def timed_run(prob, steps, warmup, variant=None, width=None):
     t1 = time.perf_counter()
     kernel_ms, launches, alg_bytes = s.profile_end()
     wall = t1 - t0
+    # the same steps again from the initial state with the launches replayed
+    # from HIP graphs (per-launch profiling is off): same end state, bit for bit
+    s.reset()
+    s.advance(warm)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.advance(steps)
+    s.synchronize()
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t2
     v, tx, ty = s.variant()
     w = s.chunk_width()
     # plain P_N, time-independent data: one advance of k steps launches the odd
@@ -313,6 +331,7 @@ def timed_run(prob, steps, warmup, variant=None, width=None):
                      "hbm_GBs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
                      "traffic_over_algorithmic": traffic / per_launch if traffic else None,
                      "effective_GBs": 3 * SIZE[prec] * updates / wall / 1e9},
+        "graph_replay": {"value": updates / wall_graph, "ms_per_step": wall_graph / steps * 1e3},
     }
     return s, rec
 
@@ -410,7 +429,9 @@ def main():
     ap.add_argument("--variant", type=int, default=None,
                     help="sweep tile variant (default: the one of the committed counter summary, else autotune)")
     ap.add_argument("--width", type=int, default=None, help="m-range width with --variant")
-    ap.add_argument("--cpu-rows", type=int, default=200, help="rows of the oracle's CPU sample")
+    ap.add_argument("--cpu-rows", type=int, default=1000,
+                    help="rows of the oracle's CPU sample (all rows: the whole workload)")
+    ap.add_argument("--cpu-steps", type=int, default=6, help="full steps of the oracle's CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0: skip it)")
     ap.add_argument("--fused-steps", type=int, default=20,
@@ -511,7 +532,7 @@ def main():
     if args.closure > 0:
         out["closure"] = closure_leg(args.closure)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_rows, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

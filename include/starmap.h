@@ -462,11 +462,14 @@ int starmap_reset(starmap_solver* s);
 /* ------------------------------------------------------------------- batches */
 
 /* A batch advances several independent solvers together on one device:
-   sweep number j of the fused composition (see starmap_advance; sweep j is
-   odd for even j) runs as ONE kernel launch over the tiles of every instance
-   that still has sweeps left, so instances of different orders N, grid sizes
-   and step counts share the machine, and a whole run is captured in one HIP
-   graph.  The solvers must share the storage precision, have time-independent
+   instances are grouped by moment order N, and sweep number j of the fused
+   composition (see starmap_advance; sweep j is odd for even j) runs as one
+   kernel launch per group over the tiles of the group's instances that still
+   have sweeps left, so instances of different grid sizes and step counts share
+   the machine, each group has its own tile, and a whole run is captured in
+   one HIP graph.  With several groups each group's launches form a chain on a
+   stream of its own (forked from and joined into the batch's stream), so the
+   groups' launches may run concurrently.  The solvers must share the storage precision, have time-independent
    data, and outlive the batch; their results are read with the per-solver
    calls.  A batch holds either no closure solvers or only closure solvers
    (STARMAP_CLOSURE_LEARNED, network loaded, one network for all): then every
@@ -491,13 +494,29 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph);
 int starmap_batch_last_run(const starmap_batch* b, double* ms, int64_t* updates, double* bytes,
                            int64_t* launches);
 
-/* Tile variant and m-range width (4, 6 or 8) shared by the batch; the default
-   is variant 0 with width 8.  starmap_batch_autotune times every pair that
-   fits on a few sub-step-0 sweeps of the whole batch (state unchanged) and
-   keeps the fastest. */
+/* Tile variant and m-range width (4, 6 or 8) per group; the default is
+   variant 0 with width 8 for every group.  starmap_batch_set_variant gives
+   every group the same pair (STARMAP_EINVAL if it does not fit the LDS for
+   one of them).  starmap_batch_get_variant reports the pair of the group with
+   the most cell-moment work (-1 and 0 before the first device call).
+   starmap_batch_autotune times, for each group on its own, every pair that
+   fits on a few sweeps with sub-step length 0 (state unchanged) and keeps the
+   group's fastest. */
 int starmap_batch_set_variant(starmap_batch* b, int32_t variant, int32_t width);
 int starmap_batch_get_variant(const starmap_batch* b, int32_t* variant, int32_t* width);
 int starmap_batch_autotune(starmap_batch* b, int32_t sweeps_per_variant);
+
+/* Groups, by ascending order N: starmap_batch_group_count returns their
+   number (or a negative error code); starmap_batch_get_group reports group
+   `group`'s order, instance count, variant and width (-1 and 0 before the
+   first device call); any output pointer may be NULL. */
+int starmap_batch_group_count(const starmap_batch* b);
+int starmap_batch_get_group(const starmap_batch* b, int32_t group, int32_t* N, int32_t* count, int32_t* variant,
+                            int32_t* width);
+
+/* Tile variant and m-range width of one group only (errors as
+   starmap_batch_set_variant; STARMAP_EINVAL for a group out of range). */
+int starmap_batch_set_group_variant(starmap_batch* b, int32_t group, int32_t variant, int32_t width);
 
 const char* starmap_last_error(void);
 

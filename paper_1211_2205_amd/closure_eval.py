@@ -10,7 +10,9 @@ the batch's autotuned tile; closure solvers use the batched fused closure
 sweep), timed by device events around the graph launch (best of `repeats`
 runs after an untimed one); the ratio of two models' times is their ratio of
 throughput on the same work.  Single-instance times (graph-captured advance,
-wall clock of the stepping loop) are reported beside it for a few instances.
+wall clock of the stepping loop) are reported beside it for a few instances,
+for the closure model both with the network and the odd update as two kernels
+(the single-solver default) and fused into one.
 
     python -m paper_1211_2205_amd.closure_eval --weights weights.npy --count 64
 """
@@ -56,8 +58,10 @@ def _batch(probs, closure_params=None, repeats=3):
     return r00, best_ms, best_wall, rec["updates"]
 
 
-def _single(prob, closure_params=None):
+def _single(prob, closure_params=None, fused=False):
     s = _make(prob, closure_params)
+    if fused:
+        s.set_closure_fused(True)
     s.run()  # untimed: device set-up and graph capture
     s.reset()
     s.synchronize()
@@ -90,8 +94,10 @@ def evaluate(params, seeds, n=256, ref_order=31, singles=8, log=print):
             f"P5+closure {row['err_p5_closure']:.3e}")
     single = {}
     if singles > 0:
-        for label, N, cl in (("p5", 5, None), ("p9", 9, None), ("p5_closure", 5, params)):
-            single[label] = float(np.mean([_single(wl.closure_instance(k, N, n), cl) for k in seeds[:singles]]))
+        for label, N, cl, fused in (("p5", 5, None, False), ("p9", 9, None, False), ("p5_closure", 5, params, False),
+                                    ("p5_closure_fused", 5, params, True)):
+            single[label] = float(np.mean([_single(wl.closure_instance(k, N, n), cl, fused)
+                                           for k in seeds[:singles]]))
     e5 = np.array([r["err_p5"] for r in rows])
     e9 = np.array([r["err_p9"] for r in rows])
     ec = np.array([r["err_p5_closure"] for r in rows])

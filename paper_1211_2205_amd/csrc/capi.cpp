@@ -1753,27 +1753,46 @@ extern "C" int starmap_reset(starmap_solver* s) {
 
 // ------------------------------------------------------------ batches
 // A batch advances several independent solvers together: every sweep number
-// j of the fused composition is one launch over the workgroups of all
-// instances still running, and the whole run is one HIP graph.
+// j of the fused composition is one launch per group of instances over the
+// workgroups of the group's instances still running, and the whole run is one
+// HIP graph.  Instances are grouped by moment order N; each group has its own
+// tile variant and m-range width (the autotuner picks them per group).
+
+namespace starmap {
+namespace detail {
+struct BatchGroup {
+  int N = 0;
+  std::vector<int> members;   // instance indices, in the caller's order
+  int variant = -1, width = 0, slots = 0;
+  bool tiles_set = false;
+  // launch plan of the current table
+  std::vector<int> order;     // members with sweeps left, by sweeps (descending, stable)
+  std::vector<int> nsweeps;
+  std::vector<int> first;     // workgroup prefix (order.size() + 1 values)
+  size_t tab0 = 0;            // first table entry of the group
+  size_t first0 = 0;          // first prefix value of the group in the table's int array
+};
+}  // namespace detail
+}  // namespace starmap
 
 struct starmap_batch {
   std::vector<starmap_solver*> inst;  // as given by the caller
   int storage = STORE_FP64;
-  int variant = -1, width = 0;  // one tile variant and m-range width for all instances
-  int slots = 0;                // LDS planes of the largest instance
-  bool tiles_set = false;
+  std::vector<starmap::detail::BatchGroup> groups;  // by ascending N
   hipStream_t stream = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  void* dtab = nullptr;  // BatchEntry[count], then int first[count + 1]
-  // batches of closure solvers: ClosureInst[count], then int cfirst[count + 1]
-  // (evaluation blocks of the closure sweep per instance, sorted order)
+  // one stream per group: a run forks from `stream` into the groups' chains
+  // of launches (independent instances) and joins back
+  std::vector<hipStream_t> gstream;
+  std::vector<hipEvent_t> gdone;
+  hipEvent_t fork = nullptr;
+  void* dtab = nullptr;  // BatchEntry[count], then the groups' workgroup prefixes
+  // batches of closure solvers (one group, N = 5): ClosureInst[count], then
+  // int cfirst[count + 1] (evaluation blocks of the closure sweep per
+  // instance, in the group's order)
   bool closure = false;
   void* ctab = nullptr;
   std::vector<int> cfirst;
-  // launch plan of the current table: sorted instances, sweeps, workgroup prefix
-  std::vector<int> order;
-  std::vector<int> nsweeps;
-  std::vector<int> first;
   // captured run
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1786,7 +1805,9 @@ struct starmap_batch {
 namespace starmap {
 namespace detail {
 
-size_t batch_table_bytes(int count) { return align256(size_t(count) * sizeof(BatchEntry)) + size_t(count + 1) * 4; }
+size_t batch_table_bytes(int count, int ngroups) {
+  return align256(size_t(count) * sizeof(BatchEntry)) + size_t(count + ngroups) * 4;
+}
 size_t closure_table_bytes(int count) {
   return align256(size_t(count) * sizeof(ClosureInst)) + size_t(count + 1) * 4;
 }
@@ -1822,14 +1843,14 @@ int batch_devices(starmap_batch* b) {
   return STARMAP_OK;
 }
 
-// ... and the shared tile of every instance.
-int batch_prepare(starmap_batch* b, int variant, int width) {
+// The tile of one group: every member's programs for it, the group's LDS.
+int group_prepare(starmap_batch* b, BatchGroup& g, int variant, int width) {
   int rc = batch_devices(b);
   if (rc) return rc;
-  if (b->tiles_set && variant == b->variant && width == b->width) return STARMAP_OK;
-  const int max_lds = max_lds_bytes();
+  if (g.tiles_set && variant == g.variant && width == g.width) return STARMAP_OK;
   int slots = 0;
-  for (auto* s : b->inst) {
+  for (int i : g.members) {
+    starmap_solver* s = b->inst[i];
     s->variant = variant;
     s->chunk_width = width;
     rc = upload_program(s);
@@ -1838,14 +1859,31 @@ int batch_prepare(starmap_batch* b, int variant, int width) {
       return fail(STARMAP_ESTATE, "sweep programs of the two parities differ in m ranges");
     slots = std::max(slots, s->slots);
   }
-  b->tiles_set = true;
-  b->variant = variant;
-  b->width = width;
-  b->slots = slots;
+  g.tiles_set = true;
+  g.variant = variant;
+  g.width = width;
+  g.slots = slots;
   drop_graph(b);
-  if (sweep_lds_bytes(variant, slots, b->storage) > size_t(max_lds))
-    return fail(STARMAP_EINVAL, "tile variant does not fit the LDS for the largest moment order of the batch");
+  if (sweep_lds_bytes(variant, slots, b->storage) > size_t(max_lds_bytes()))
+    return fail(STARMAP_EINVAL, "tile variant does not fit the LDS for the moment order of a batch group");
   HIP_TRY(prepare_sweep(b->storage, variant, slots));
+  return STARMAP_OK;
+}
+
+// ... every group with the same tile, or the default tile where none is set.
+int batch_prepare(starmap_batch* b, int variant, int width) {
+  for (auto& g : b->groups) {
+    int rc = group_prepare(b, g, variant, width);
+    if (rc) return rc;
+  }
+  return STARMAP_OK;
+}
+
+int batch_ready(starmap_batch* b) {
+  for (auto& g : b->groups) {
+    int rc = group_prepare(b, g, g.tiles_set ? g.variant : 0, g.tiles_set ? g.width : kDefaultChunkWidth);
+    if (rc) return rc;
+  }
   return STARMAP_OK;
 }
 
@@ -1855,70 +1893,82 @@ int items_of(const starmap_solver* s) {
   return ntx * nty * int(s->prog[0].chunks.size());
 }
 
-// Entries of the instances with sweeps[i] > 0, sorted by sweeps (descending,
-// stable), uploaded with their workgroup prefix.  zero_tau: every sub-step
-// length 0 (timing on live state leaves it unchanged).
+// Per group, the entries of the members with sweeps[i] > 0 sorted by sweeps
+// (descending, stable), uploaded with the group's workgroup prefix.
+// zero_tau: every sub-step length 0 (timing on live state leaves it unchanged).
 int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau) {
   const int count = int(b->inst.size());
-  std::vector<int> ord;
-  for (int i = 0; i < count; ++i)
-    if (sweeps[i] > 0) ord.push_back(i);
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sweeps[x] > sweeps[y]; });
-  std::vector<BatchEntry> tab(ord.size());
-  std::vector<int> first(ord.size() + 1, 0);
-  int64_t total = 0;
-  for (size_t r = 0; r < ord.size(); ++r) {
-    starmap_solver* s = b->inst[ord[r]];
-    BatchEntry& e = tab[r];
-    std::memset(&e, 0, sizeof(e));
-    e.u = dptr(s, s->off_state);
-    e.decay = dptr(s, s->off_decay);
-    for (int p = 0; p < 2; ++p) {
-      const auto& pr = s->prog[p];
-      char* base = dptr(s, s->off_prog[p]);
-      size_t o = 0;
-      e.chunks[p] = reinterpret_cast<const int4*>(base + o);
-      o += align256(pr.chunks.size() * 16);
-      e.orders[p] = reinterpret_cast<const int4*>(base + o);
-      o += align256(pr.orders.size() * 16);
-      e.loads[p] = reinterpret_cast<const int4*>(base + o);
-      o += align256(pr.loads.size() * 16);
-      e.rows[p] = reinterpret_cast<const int*>(base + o);
-      o += align256(pr.rows.size() * 64);
-      e.rcoef[p] = base + o;
-      e.zero_off[p] = pr.zero_off;
-    }
-    e.plane_stride = s->plane_stride;
-    e.tau_full = zero_tau ? 0.0 : s->dt;
-    e.tau_half = zero_tau ? 0.0 : 0.5 * s->dt;
-    e.pitch = s->pitch;
-    e.nx = s->nx;
-    e.ny = s->ny;
-    e.px = s->px;
-    e.py = s->py;
-    const TileShape ts = sweep_variant(s->variant);
-    e.ntx = (s->nx + 1 + ts.tx - 1) / ts.tx;
-    e.nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
-    e.nchunks = int(s->prog[0].chunks.size());
-    e.nsweeps = sweeps[ord[r]];
-    e.strip = s->tile_strip;
-    e.even_b_delta = s->closure ? int64_t(s->off_prog_b) - int64_t(s->off_prog[0]) : 0;
-    first[r] = int(total);
-    total += items_of(s);
-  }
-  if (total >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "too many workgroups in one batched sweep");
-  first[ord.size()] = int(total);
-  std::vector<char> buf(batch_table_bytes(count), 0);
-  std::memcpy(buf.data(), tab.data(), tab.size() * sizeof(BatchEntry));
-  std::memcpy(buf.data() + align256(size_t(count) * sizeof(BatchEntry)), first.data(), first.size() * 4);
-  HIP_TRY(hipMemcpyAsync(b->dtab, buf.data(), buf.size(), hipMemcpyHostToDevice, b->stream));
-  if (b->closure) {
-    // the closure sweep's instances in the same order, with their block prefix
-    std::vector<ClosureInst> ct(ord.size());
-    std::vector<int> cf(ord.size() + 1, 0);
-    int64_t nb = 0;
+  const int ng = int(b->groups.size());
+  std::vector<BatchEntry> tab;
+  std::vector<int> firsts;
+  for (auto& g : b->groups) {
+    std::vector<int> ord;
+    for (int i : g.members)
+      if (sweeps[i] > 0) ord.push_back(i);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sweeps[x] > sweeps[y]; });
+    g.tab0 = tab.size();
+    g.first0 = firsts.size();
+    g.order = ord;
+    g.nsweeps.assign(ord.size(), 0);
+    g.first.assign(ord.size() + 1, 0);
+    int64_t total = 0;
     for (size_t r = 0; r < ord.size(); ++r) {
       starmap_solver* s = b->inst[ord[r]];
+      BatchEntry e;
+      std::memset(&e, 0, sizeof(e));
+      e.u = dptr(s, s->off_state);
+      e.decay = dptr(s, s->off_decay);
+      for (int p = 0; p < 2; ++p) {
+        const auto& pr = s->prog[p];
+        char* base = dptr(s, s->off_prog[p]);
+        size_t o = 0;
+        e.chunks[p] = reinterpret_cast<const int4*>(base + o);
+        o += align256(pr.chunks.size() * 16);
+        e.orders[p] = reinterpret_cast<const int4*>(base + o);
+        o += align256(pr.orders.size() * 16);
+        e.loads[p] = reinterpret_cast<const int4*>(base + o);
+        o += align256(pr.loads.size() * 16);
+        e.rows[p] = reinterpret_cast<const int*>(base + o);
+        o += align256(pr.rows.size() * 64);
+        e.rcoef[p] = base + o;
+        e.zero_off[p] = pr.zero_off;
+      }
+      e.plane_stride = s->plane_stride;
+      e.tau_full = zero_tau ? 0.0 : s->dt;
+      e.tau_half = zero_tau ? 0.0 : 0.5 * s->dt;
+      e.pitch = s->pitch;
+      e.nx = s->nx;
+      e.ny = s->ny;
+      e.px = s->px;
+      e.py = s->py;
+      const TileShape ts = sweep_variant(s->variant);
+      e.ntx = (s->nx + 1 + ts.tx - 1) / ts.tx;
+      e.nty = (s->ny + 1 + ts.ty - 1) / ts.ty;
+      e.nchunks = int(s->prog[0].chunks.size());
+      e.nsweeps = sweeps[ord[r]];
+      e.strip = s->tile_strip;
+      e.even_b_delta = s->closure ? int64_t(s->off_prog_b) - int64_t(s->off_prog[0]) : 0;
+      tab.push_back(e);
+      g.nsweeps[r] = sweeps[ord[r]];
+      g.first[r] = int(total);
+      total += items_of(s);
+    }
+    if (total >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "too many workgroups in one batched sweep");
+    g.first[ord.size()] = int(total);
+    firsts.insert(firsts.end(), g.first.begin(), g.first.end());
+  }
+  std::vector<char> buf(batch_table_bytes(count, ng), 0);
+  std::memcpy(buf.data(), tab.data(), tab.size() * sizeof(BatchEntry));
+  std::memcpy(buf.data() + align256(size_t(count) * sizeof(BatchEntry)), firsts.data(), firsts.size() * 4);
+  HIP_TRY(hipMemcpyAsync(b->dtab, buf.data(), buf.size(), hipMemcpyHostToDevice, b->stream));
+  if (b->closure) {
+    // the closure sweep's instances in the (single) group's order, with their block prefix
+    const BatchGroup& g = b->groups[0];
+    std::vector<ClosureInst> ct(g.order.size());
+    std::vector<int> cf(g.order.size() + 1, 0);
+    int64_t nb = 0;
+    for (size_t r = 0; r < g.order.size(); ++r) {
+      starmap_solver* s = b->inst[g.order[r]];
       ClosureInst& c = ct[r];
       std::memset(&c, 0, sizeof(c));
       const size_t pb = s->plane_bytes_state();
@@ -1928,14 +1978,14 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
       c.decay = dptr(s, s->off_decay);
       c.tau_full = zero_tau ? 0.0 : s->dt;
       c.tau_half = zero_tau ? 0.0 : 0.5 * s->dt;
-      c.nsweeps = sweeps[ord[r]];
+      c.nsweeps = sweeps[g.order[r]];
       c.G = s->cgeo;
       c.odd = s->codd;
       cf[r] = int(nb);
       nb += closure_blocks_of(s);
     }
     if (nb >= (int64_t(1) << 31)) return fail(STARMAP_EINVAL, "too many closure blocks in one batched sweep");
-    cf[ord.size()] = int(nb);
+    cf[g.order.size()] = int(nb);
     std::vector<char> cb(closure_table_bytes(count), 0);
     std::memcpy(cb.data(), ct.data(), ct.size() * sizeof(ClosureInst));
     std::memcpy(cb.data() + align256(size_t(count) * sizeof(ClosureInst)), cf.data(), cf.size() * 4);
@@ -1943,34 +1993,85 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
     b->cfirst = cf;
   }
   HIP_TRY(hipStreamSynchronize(b->stream));
-  b->order = ord;
-  b->nsweeps.resize(ord.size());
-  for (size_t r = 0; r < ord.size(); ++r) b->nsweeps[r] = sweeps[ord[r]];
-  b->first = first;
   return STARMAP_OK;
 }
 
-// Queue sweeps j0 .. j1-1 of the current table on the batch stream.
-int batch_launch(starmap_batch* b, int j0, int j1) {
+// Queue sweeps j0 .. j1-1 of the current table on the batch stream: one
+// launch per group with instances still running (only group `only` if >= 0).
+int batch_launch(starmap_batch* b, int j0, int j1, int only = -1) {
   const BatchEntry* tab = reinterpret_cast<const BatchEntry*>(b->dtab);
-  const int* first =
+  const int* firsts =
       reinterpret_cast<const int*>(static_cast<char*>(b->dtab) + align256(b->inst.size() * sizeof(BatchEntry)));
-  int n_active = int(b->nsweeps.size());
   for (int j = j0; j < j1; ++j) {
-    while (n_active > 0 && b->nsweeps[n_active - 1] <= j) --n_active;
-    if (n_active == 0) break;
     if (b->closure && (j & 1) == 0) {
       // odd sweep of closure solvers: the network and the odd update in one kernel
+      const BatchGroup& g = b->groups[0];
+      int na = int(g.nsweeps.size());
+      while (na > 0 && g.nsweeps[na - 1] <= j) --na;
+      if (na == 0) continue;
       const ClosureInst* ct = reinterpret_cast<const ClosureInst*>(b->ctab);
       const int* cf = reinterpret_cast<const int*>(static_cast<char*>(b->ctab) +
                                                    align256(b->inst.size() * sizeof(ClosureInst)));
-      const starmap_solver* s0 = b->inst[b->order[0]];
-      HIP_TRY(launch_closure_batch(b->storage, ct, cf, n_active, b->cfirst[n_active], j,
+      const starmap_solver* s0 = b->inst[g.order[0]];
+      HIP_TRY(launch_closure_batch(b->storage, ct, cf, na, b->cfirst[na], j,
                                    reinterpret_cast<const ClosureNet*>(dptr(s0, s0->off_net)), b->stream));
       continue;
     }
-    HIP_TRY(launch_sweep_batch(b->storage, b->variant, tab, first, n_active, b->first[n_active], j, b->slots,
-                               b->stream));
+    for (int gi = 0; gi < int(b->groups.size()); ++gi) {
+      if (only >= 0 && gi != only) continue;
+      const BatchGroup& g = b->groups[gi];
+      int na = int(g.nsweeps.size());
+      while (na > 0 && g.nsweeps[na - 1] <= j) --na;
+      if (na == 0) continue;
+      HIP_TRY(launch_sweep_batch(b->storage, g.variant, tab + g.tab0, firsts + g.first0, na, g.first[na], j,
+                                 g.slots, b->stream));
+    }
+  }
+  return STARMAP_OK;
+}
+
+// Cell-moment work of a group for one step of every member (for reporting the
+// dominant group's tile).
+double group_work(const starmap_batch* b, const BatchGroup& g) {
+  double w = 0.0;
+  for (int i : g.members) {
+    const starmap_solver* s = b->inst[i];
+    w += double(s->nmom) * s->nx * s->ny * double(s->steps_total);
+  }
+  return w;
+}
+
+// Every sweep of a run: a single group (or a closure batch) on the batch
+// stream; several groups each as its own chain on its own stream, forked from
+// and joined back into the batch stream, so that one group's launches fill
+// the machine while another's drain.
+int batch_launch_all(starmap_batch* b, int jmax) {
+  if (b->closure || b->groups.size() == 1) return batch_launch(b, 0, jmax);
+  const BatchEntry* tab = reinterpret_cast<const BatchEntry*>(b->dtab);
+  const int* firsts =
+      reinterpret_cast<const int*>(static_cast<char*>(b->dtab) + align256(b->inst.size() * sizeof(BatchEntry)));
+  // the groups with the most work first: the chains start one after another
+  // as the machine frees up, and the longest one bounds the run
+  std::vector<int> ord(b->groups.size());
+  for (size_t gi = 0; gi < ord.size(); ++gi) ord[gi] = int(gi);
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int x, int y) { return group_work(b, b->groups[x]) > group_work(b, b->groups[y]); });
+  HIP_TRY(hipEventRecord(b->fork, b->stream));
+  for (int gi : ord) HIP_TRY(hipStreamWaitEvent(b->gstream[gi], b->fork, 0));
+  // submitted sweep by sweep across the groups (a chain submitted whole could
+  // fill its queue and hold back the next)
+  for (int j = 0; j < jmax; ++j)
+    for (int gi : ord) {
+      const BatchGroup& g = b->groups[gi];
+      int na = int(g.nsweeps.size());
+      while (na > 0 && g.nsweeps[na - 1] <= j) --na;
+      if (na == 0) continue;
+      HIP_TRY(launch_sweep_batch(b->storage, g.variant, tab + g.tab0, firsts + g.first0, na, g.first[na], j,
+                                 g.slots, b->gstream[gi]));
+    }
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    HIP_TRY(hipEventRecord(b->gdone[gi], b->gstream[gi]));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->gdone[gi], 0));
   }
   return STARMAP_OK;
 }
@@ -2011,11 +2112,33 @@ int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_
   auto b = std::make_unique<starmap_batch>();
   b->inst = v;
   b->storage = v[0]->storage;
+  b->closure = v[0]->closure;
+  {
+    std::vector<int> orders;
+    for (auto* s : v) orders.push_back(s->N);
+    std::sort(orders.begin(), orders.end());
+    orders.erase(std::unique(orders.begin(), orders.end()), orders.end());
+    for (int N : orders) {
+      BatchGroup g;
+      g.N = N;
+      for (int i = 0; i < count; ++i)
+        if (v[i]->N == N) g.members.push_back(i);
+      b->groups.push_back(g);
+    }
+  }
   HIP_TRY(hipStreamCreate(&b->stream));
   HIP_TRY(hipEventCreate(&b->ev[0]));
   HIP_TRY(hipEventCreate(&b->ev[1]));
-  HIP_TRY(hipMalloc(&b->dtab, batch_table_bytes(count)));
-  b->closure = v[0]->closure;
+  if (!b->closure && b->groups.size() > 1) {
+    HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    b->gstream.assign(b->groups.size(), nullptr);
+    b->gdone.assign(b->groups.size(), nullptr);
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      HIP_TRY(hipStreamCreate(&b->gstream[gi]));
+      HIP_TRY(hipEventCreateWithFlags(&b->gdone[gi], hipEventDisableTiming));
+    }
+  }
+  HIP_TRY(hipMalloc(&b->dtab, batch_table_bytes(count, int(b->groups.size()))));
   if (b->closure) HIP_TRY(hipMalloc(&b->ctab, closure_table_bytes(count)));
   *out = b.release();
   return STARMAP_OK;
@@ -2024,11 +2147,18 @@ int starmap_batch_create(starmap_solver* const* solvers, int32_t count, starmap_
 void starmap_batch_destroy(starmap_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto st : b->gstream)
+    if (st) (void)hipStreamSynchronize(st);
   drop_graph(b);
   if (b->dtab) (void)hipFree(b->dtab);
   if (b->ctab) (void)hipFree(b->ctab);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto e : b->gdone)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (auto st : b->gstream)
+    if (st) (void)hipStreamDestroy(st);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
@@ -2041,16 +2171,52 @@ int starmap_batch_set_variant(starmap_batch* b, int32_t variant, int32_t width) 
   return batch_prepare(b, variant, width);
 }
 
+int starmap_batch_set_group_variant(starmap_batch* b, int32_t group, int32_t variant, int32_t width) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  if (group < 0 || group >= int32_t(b->groups.size())) return fail(STARMAP_EINVAL, "group out of range");
+  if (variant < 0 || variant >= sweep_variant_count()) return fail(STARMAP_EINVAL, "unknown variant");
+  if (std::find(std::begin(kChunkWidths), std::end(kChunkWidths), width) == std::end(kChunkWidths))
+    return fail(STARMAP_EINVAL, "unsupported m-range width");
+  return group_prepare(b, b->groups[group], variant, width);
+}
+
 int starmap_batch_get_variant(const starmap_batch* b, int32_t* variant, int32_t* width) {
   if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
-  if (variant) *variant = b->tiles_set ? b->variant : -1;
-  if (width) *width = b->tiles_set ? b->width : 0;
+  // the group with the most cell-moment work
+  const BatchGroup* best = nullptr;
+  double wmax = -1.0;
+  for (const auto& g : b->groups) {
+    const double w = group_work(b, g);
+    if (w > wmax) {
+      wmax = w;
+      best = &g;
+    }
+  }
+  if (variant) *variant = best && best->tiles_set ? best->variant : -1;
+  if (width) *width = best && best->tiles_set ? best->width : 0;
+  return STARMAP_OK;
+}
+
+int starmap_batch_group_count(const starmap_batch* b) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  return int(b->groups.size());
+}
+
+int starmap_batch_get_group(const starmap_batch* b, int32_t group, int32_t* N, int32_t* count, int32_t* variant,
+                            int32_t* width) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  if (group < 0 || group >= int32_t(b->groups.size())) return fail(STARMAP_EINVAL, "group out of range");
+  const BatchGroup& g = b->groups[group];
+  if (N) *N = g.N;
+  if (count) *count = int32_t(g.members.size());
+  if (variant) *variant = g.tiles_set ? g.variant : -1;
+  if (width) *width = g.tiles_set ? g.width : 0;
   return STARMAP_OK;
 }
 
 int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
   if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
-  int rc = batch_prepare(b, b->tiles_set ? b->variant : 0, b->tiles_set ? b->width : kDefaultChunkWidth);
+  int rc = batch_ready(b);
   if (rc) return rc;
   rc = batch_sync_solvers(b);
   if (rc) return rc;
@@ -2068,26 +2234,28 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
   }
   rc = batch_table(b, sweeps, false);
   if (rc) return rc;
-  const int jmax = b->nsweeps.empty() ? 0 : b->nsweeps[0];
+  int jmax = 0;
   int64_t launches = 0;
-  {
-    int na = int(b->nsweeps.size());
-    for (int j = 0; j < jmax; ++j) {
-      while (na > 0 && b->nsweeps[na - 1] <= j) --na;
-      launches += na > 0;
-    }
+  for (const auto& g : b->groups) {
+    if (!g.nsweeps.empty()) jmax = std::max(jmax, g.nsweeps[0]);
+    for (int j = 0; !g.nsweeps.empty() && j < g.nsweeps[0]; ++j)
+      if (!(b->closure && (j & 1) == 0)) ++launches;
   }
+  if (b->closure && !b->groups[0].nsweeps.empty()) launches += (b->groups[0].nsweeps[0] + 1) / 2;
   HIP_TRY(hipEventRecord(b->ev[0], b->stream));
   if (jmax > 0) {
     if (use_graph) {
-      // the graph depends on the tile (kernel, LDS) and on the launch plan
-      std::vector<int> key = {b->variant, b->width, b->slots};
-      key.insert(key.end(), b->nsweeps.begin(), b->nsweeps.end());
-      key.insert(key.end(), b->first.begin(), b->first.end());
+      // the graph depends on every group's tile (kernel, LDS) and launch plan
+      std::vector<int> key;
+      for (const auto& g : b->groups) {
+        key.insert(key.end(), {g.variant, g.width, g.slots, int(g.nsweeps.size())});
+        key.insert(key.end(), g.nsweeps.begin(), g.nsweeps.end());
+        key.insert(key.end(), g.first.begin(), g.first.end());
+      }
       if (!b->exec || key != b->graph_key) {
         drop_graph(b);
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        rc = batch_launch(b, 0, jmax);
+        rc = batch_launch_all(b, jmax);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b->stream, &g);
         if (rc) {
@@ -2103,7 +2271,7 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
       }
       HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     } else {
-      rc = batch_launch(b, 0, jmax);
+      rc = batch_launch_all(b, jmax);
       if (rc) return rc;
     }
   }
@@ -2111,11 +2279,12 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
   HIP_TRY(hipEventSynchronize(b->ev[1]));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
-  for (size_t r = 0; r < b->order.size(); ++r) {
-    starmap_solver* s = b->inst[b->order[r]];
-    if (b->closure) {
+  if (b->closure) {
+    const BatchGroup& g = b->groups[0];
+    for (size_t r = 0; r < g.order.size(); ++r) {
+      starmap_solver* s = b->inst[g.order[r]];
       // (nsweeps + 1) / 2 odd sweeps each moved the order-5 moments once
-      s->c5_flip = ((b->nsweeps[r] + 1) / 2) & 1;
+      s->c5_flip = ((g.nsweeps[r] + 1) / 2) & 1;
       rc = closure_settle(s);
       if (rc) return rc;
       HIP_TRY(hipStreamSynchronize(s->stream));
@@ -2147,59 +2316,66 @@ int starmap_batch_autotune(starmap_batch* b, int32_t sweeps) {
   const int count = int(b->inst.size());
   const int max_lds = max_lds_bytes();
   {
-    int rc = batch_devices(b);
+    int rc = batch_ready(b);
     if (rc) return rc;
   }
-  int best_v = -1, best_w = 0;
-  float best_ms = 0.f;
-  std::vector<std::vector<int>> tried;
-  for (int w : kChunkWidths) {
-    std::vector<int> split;
-    for (auto* s : b->inst) split.push_back(sweep_chunk_count(s->N, w));
-    if (std::find(tried.begin(), tried.end(), split) != tried.end()) continue;  // same m ranges as a narrower width
-    tried.push_back(split);
-    for (int v = 0; v < sweep_variant_count(); ++v) {
-      // LDS check before the kernels are opted in
-      int slots = 0;
-      for (auto* s : b->inst) {
-        s->variant = v;
-        s->chunk_width = w;
-        int rc = upload_program(s);
+  // each group on its own: every (width, variant) pair that fits, timed on a
+  // sweep pair of the group's instances (tau = 0 leaves every value unchanged)
+  for (int gi = 0; gi < int(b->groups.size()); ++gi) {
+    BatchGroup& g = b->groups[gi];
+    int best_v = -1, best_w = 0;
+    float best_ms = 0.f;
+    std::vector<int> tried;
+    for (int w : kChunkWidths) {
+      const int split = sweep_chunk_count(g.N, w);
+      if (std::find(tried.begin(), tried.end(), split) != tried.end()) continue;  // same m ranges as a narrower width
+      tried.push_back(split);
+      for (int v = 0; v < sweep_variant_count(); ++v) {
+        // LDS check before the kernels are opted in
+        int slots = 0;
+        for (int i : g.members) {
+          starmap_solver* s = b->inst[i];
+          s->variant = v;
+          s->chunk_width = w;
+          int rc = upload_program(s);
+          if (rc) return rc;
+          slots = std::max(slots, s->slots);
+        }
+        g.tiles_set = false;
+        if (sweep_lds_bytes(v, slots, b->storage) > size_t(max_lds)) continue;
+        int rc = group_prepare(b, g, v, w);
         if (rc) return rc;
-        slots = std::max(slots, s->slots);
-      }
-      b->tiles_set = false;
-      if (sweep_lds_bytes(v, slots, b->storage) > size_t(max_lds)) continue;
-      int rc = batch_prepare(b, v, w);
-      if (rc) return rc;
-      // tau = 0 leaves every value unchanged; three sweeps: odd, even, odd.
-      // A closure batch times the first pair (odd sweep 0 copies the order-5
-      // moments into the closure planes, even sweep 1 reads them there)
-      const int j0 = b->closure ? 0 : 1;
-      rc = batch_table(b, std::vector<int>(count, 3), true);
-      if (!rc) rc = batch_launch(b, j0, j0 + 2);
-      if (rc) return rc;
-      HIP_TRY(hipEventRecord(b->ev[0], b->stream));
-      for (int i = 0; i < sweeps && !rc; ++i) rc = batch_launch(b, j0, j0 + 2);
-      if (rc) return rc;
-      HIP_TRY(hipEventRecord(b->ev[1], b->stream));
-      HIP_TRY(hipEventSynchronize(b->ev[1]));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
-      if (std::getenv("STARMAP_VERBOSE")) {
-        const TileShape ts = sweep_variant(v);
-        std::fprintf(stderr, "starmap batch autotune: width %d variant %d (%dx%d) %.3f ms per sweep pair\n", w, v,
-                     ts.tx, ts.ty, ms / sweeps);
-      }
-      if (best_v < 0 || ms < best_ms) {
-        best_v = v;
-        best_w = w;
-        best_ms = ms;
+        // three sweeps: odd, even, odd.  A closure batch times the first pair
+        // (odd sweep 0 copies the order-5 moments into the closure planes,
+        // even sweep 1 reads them there)
+        const int j0 = b->closure ? 0 : 1;
+        rc = batch_table(b, std::vector<int>(count, 3), true);
+        if (!rc) rc = batch_launch(b, j0, j0 + 2, gi);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+        for (int i = 0; i < sweeps && !rc; ++i) rc = batch_launch(b, j0, j0 + 2, gi);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b->ev[1], b->stream));
+        HIP_TRY(hipEventSynchronize(b->ev[1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+        if (std::getenv("STARMAP_VERBOSE")) {
+          const TileShape ts = sweep_variant(v);
+          std::fprintf(stderr, "starmap batch autotune: N %d width %d variant %d (%dx%d) %.3f ms per sweep pair\n",
+                       g.N, w, v, ts.tx, ts.ty, ms / sweeps);
+        }
+        if (best_v < 0 || ms < best_ms) {
+          best_v = v;
+          best_w = w;
+          best_ms = ms;
+        }
       }
     }
+    if (best_v < 0) return fail(STARMAP_ENOMEM, "no sweep tile fits the LDS for a group of this batch");
+    int rc = group_prepare(b, g, best_v, best_w);
+    if (rc) return rc;
   }
-  if (best_v < 0) return fail(STARMAP_ENOMEM, "no sweep tile fits the LDS for this batch");
-  return batch_prepare(b, best_v, best_w);
+  return STARMAP_OK;
 }
 
 }  // extern "C"

@@ -410,9 +410,10 @@ class Solver:
 
 
 class Batch:
-    """Several solvers advanced together: one launch per sweep over all
-    instances still running, the whole run in one HIP graph.  The solvers must
-    outlive the batch (it keeps references to them)."""
+    """Several solvers advanced together: instances grouped by order N, one
+    launch per sweep and group over the group's instances still running, the
+    whole run in one HIP graph.  The solvers must outlive the batch (it keeps
+    references to them)."""
 
     def __init__(self, solvers):
         self.solvers = list(solvers)
@@ -445,6 +446,27 @@ class Batch:
 
     def autotune(self, sweeps=3):
         B.check(B.lib().starmap_batch_autotune(self._h, int(sweeps)))
+
+    def groups(self):
+        """Per group (ascending N): {"N", "count", "variant", "width"}."""
+        n = B.lib().starmap_batch_group_count(self._h)
+        B.check(min(n, 0))
+        out = []
+        for g in range(n):
+            N, c, v, w = (ctypes.c_int32() for _ in range(4))
+            B.check(B.lib().starmap_batch_get_group(self._h, g, ctypes.byref(N), ctypes.byref(c), ctypes.byref(v),
+                                                    ctypes.byref(w)))
+            out.append({"N": N.value, "count": c.value, "variant": v.value, "width": w.value})
+        return out
+
+    def set_group_variant(self, group, variant, width):
+        B.check(B.lib().starmap_batch_set_group_variant(self._h, int(group), int(variant), int(width)))
+
+    def tile_of(self, i):
+        """(variant, width) of the group that solver i belongs to."""
+        N = self.solvers[i].N
+        g = next(g for g in self.groups() if g["N"] == N)
+        return g["variant"], g["width"]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -56,7 +56,12 @@ def test_batch_equals_single_runs_and_oracle(monkeypatch):
     print("batch", [p.name for p in probs], steps, flush=True)
     rec = b.run(use_graph=True)
     assert b.variant() == (0, 8)
-    assert rec["launches"] == 2 * max(steps) + 1
+    # one launch per sweep and order group, for as long as the group's longest run
+    groups = b.groups()
+    assert [g["N"] for g in groups] == sorted({p.N for p in probs})
+    assert sum(g["count"] for g in groups) == len(probs)
+    assert all((g["variant"], g["width"]) == (0, 8) for g in groups)
+    assert rec["launches"] == sum(2 * max(n for s, n in zip(solvers, steps) if s.N == g["N"]) + 1 for g in groups)
     assert rec["updates"] == sum(s.nmom * p.n[0] * p.n[1] * n for s, p, n in zip(solvers, probs, steps))
     for s in solvers:
         assert s.time()[2] == s.nsteps
@@ -107,13 +112,39 @@ def test_batch_fp32_and_autotune(monkeypatch):
     solvers = [pa.Solver.from_problem(p) for p in probs]
     b = pa.Batch(solvers)
     b.autotune(2)
-    v, w = b.variant()
-    assert 0 <= v < pa.variant_count() and w in (4, 6, 8)
+    for g in b.groups():
+        assert 0 <= g["variant"] < pa.variant_count() and g["width"] in (4, 6, 8), g
     b.run()
-    for p, s in zip(probs, solvers):
+    for i, (p, s) in enumerate(zip(probs, solvers)):
+        v, w = b.tile_of(i)
         g = s.moments()
-        assert _identical(g, _single(p, v, w, monkeypatch)), p.name
+        assert _identical(g, _single(p, v, w, monkeypatch)), (p.name, v, w)
         assert_parity(g, run_oracle(p).u, 1e-5, p.name)
+    b.close()
+
+
+def test_batch_groups_with_their_own_tiles(monkeypatch):
+    """Groups of one batch on different tiles: every instance still equals its
+    single run on its group's tile, and the run is one graph relaunched."""
+    probs = _mixed()
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    b.set_variant(0, 8)
+    b.run()
+    b.reset()
+    # a different tile per group (orders 1, 2, 3, 5, 7, 9, 12)
+    choice = [(1, 4), (3, 6), (5, 4), (6, 6), (13, 4), (0, 4), (0, 6)]
+    for gi, g in enumerate(b.groups()):
+        b.set_group_variant(gi, *choice[gi % len(choice)])
+    tiles = {g["N"]: (g["variant"], g["width"]) for g in b.groups()}
+    assert len(set(tiles.values())) == len(tiles)
+    b.run(use_graph=True)
+    first = [s.moments() for s in solvers]
+    b.reset()
+    b.run(use_graph=True)
+    for p, s, f in zip(probs, solvers, first):
+        assert _identical(s.moments(), f), p.name
+        assert _identical(f, _single(p, *tiles[p.N], monkeypatch)), (p.name, tiles[p.N])
     b.close()
 
 
@@ -131,6 +162,8 @@ def test_batch_rejects_bad_input():
         b.set_variant(0, 5)
     with pytest.raises(pa.StarmapError):
         b.set_variant(17, 8)
+    with pytest.raises(pa.StarmapError):
+        b.set_group_variant(1, 0, 8)  # one group only
     b.close()
 
 
