@@ -499,6 +499,7 @@ def main():
         "data": "synthetic",
         "config": head["config"],
         "roofline": head["roofline"],
+        "graph_replay": head["graph_replay"],
         "state_check": {"mass": diag["mass"], "l2": diag["l2"], "nonfinite": diag["nonfinite"]},
     }
     legs = [p for p in args.legs.split(",") if p and p != prob.precision]
