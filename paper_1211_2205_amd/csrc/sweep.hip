@@ -22,6 +22,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -58,19 +59,20 @@ __device__ __forceinline__ const T* at(const T* base, uint32_t byte_off) {
   return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
-// Output rows are read once per sweep, just before they are overwritten.
-__device__ __forceinline__ float load_stream(const float* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ double load_stream(const double* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ bf16 load_stream(const bf16* p) {
-  return bf16{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
+// A stored value as raw bits for a register: BF16 as its 16 bits in the low
+// half of a 32-bit value (widened where it is used), other types as they are.
+// The _stream forms read output rows, which are read once per sweep, just
+// before they are overwritten.
+__device__ __forceinline__ uint32_t load_raw(const bf16* p) { return *reinterpret_cast<const uint16_t*>(p); }
+__device__ __forceinline__ float load_raw(const float* p) { return *p; }
+__device__ __forceinline__ double load_raw(const double* p) { return *p; }
+__device__ __forceinline__ uint32_t load_raw_stream(const bf16* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
 }
+__device__ __forceinline__ float load_raw_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double load_raw_stream(const double* p) { return __builtin_nontemporal_load(p); }
 
 // Two x-adjacent bfloat16 values as one 32-bit access (4-byte aligned).
-__device__ __forceinline__ void load_pair(const bf16* p, bf16& lo, bf16& hi) {
-  const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
-  lo = bf16{uint16_t(w & 0xFFFFu)};
-  hi = bf16{uint16_t(w >> 16)};
-}
 __device__ __forceinline__ uint32_t load_pair_stream(const bf16* p) {
   return __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
 }
@@ -78,8 +80,6 @@ __device__ __forceinline__ void store_pair_stream(bf16* p, bf16 lo, bf16 hi) {
   __builtin_nontemporal_store(uint32_t(lo.bits) | (uint32_t(hi.bits) << 16), reinterpret_cast<uint32_t*>(p));
 }
 // (never called for the other storage types)
-template <typename T>
-__device__ __forceinline__ void load_pair(const T*, T&, T&) {}
 template <typename T>
 __device__ __forceinline__ uint32_t load_pair_stream(const T*) { return 0; }
 template <typename T>
@@ -89,9 +89,30 @@ __device__ __forceinline__ void store_pair_stream(T*, T, T) {}
 // (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
 
+// BF16 on tiles of 512 points: each thread owns two x-adjacent points, and
+// on tiles away from the right edge of the grid (where no staging index is
+// clamped or wrapped) the pair moves as one 32-bit access: 2-byte accesses
+// would move half the bytes per instruction.
+template <typename T, int TX, int TY>
+constexpr bool kPair = sizeof(T) == 2 && TX * TY == 512;
+
+// Whether work item lb lies on a tile whose pairs all lie inside the grid
+// along x (FAST = true below); uniform over the workgroup.
+template <typename T, int TX, int TY, typename C>
+__device__ __forceinline__ bool pair_fast(const SweepScalars<C>& a, int lb) {
+  if constexpr (!kPair<T, TX, TY>) {
+    return false;
+  } else {
+    const int2 txy = tile_xy(lb / a.nchunks, a.ntx, a.nty, a.strip);
+    return txy.x * TX + TX <= a.nx;
+  }
+}
+
 // Body of one workgroup's work in a sweep: spatial tile and m range number lb
-// (lb = tile * nchunks + range) of one instance.
-template <typename T, int TX, int TY, int CAP>
+// (lb = tile * nchunks + range) of one instance.  FAST (pair tiles away from
+// the grid's right edge) is a template argument, so the pair and the single
+// accesses are separate code and no load sits under a branch on it.
+template <typename T, int TX, int TY, int CAP, bool FAST>
 __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
                                            cptr<int> chunks, cptr<int> orders, cptr<int> loads, cptr<int> rows,
                                            cptr<typename ComputeOf<T>::type> rcoef,
@@ -113,11 +134,13 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   constexpr int RB = CAP - 2;  // an m range of width w has w rows and w + 2 staged planes per order
   constexpr int LB = sizeof(T) >= 8 ? 8 : 16;  // planes per batch of the synchronous staging
   constexpr int EPT = PPT + 1;                 // staged points per thread and plane: interior + halo
-  // BF16 on tiles of 512 points: each thread owns two x-adjacent points, and
-  // on tiles away from the right edge of the grid (where no staging index
-  // is clamped or wrapped) the pair moves as one 32-bit access: 2-byte
-  // accesses would move half the bytes per instruction
-  constexpr bool PAIR = sizeof(T) == 2 && PPT == 2;
+  constexpr bool PAIR = kPair<T, TX, TY>;
+  static_assert(PAIR || !FAST, "the pair path is for BF16 tiles of 512 points");
+  // BF16 values travel from memory to their first use as raw bit patterns
+  // (16 bits in the low half of a register, or a pair as one 32-bit word):
+  // widening them right after the load would be an immediate use of the load,
+  // and its wait would hold the next order's prefetch behind the current one
+  using RW = std::conditional_t<sizeof(T) == 2, uint32_t, T>;
 
   const int tid = threadIdx.x;
   const int tile = lb / a.nchunks;
@@ -127,7 +150,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   const int x0 = txy.x * TX;
   const int y0 = txy.y * TY;
   const int grp = 0;
-  const bool pfast = PAIR && x0 + TX <= a.nx;  // uniform: every interior index maps to itself
+  constexpr bool pfast = FAST;  // every interior index of the tile maps to itself
 
   // Staging of one input plane into its (TX+1) x (TY+1) LDS tile.  The tile
   // holds global points (x0 - ox + lx, y0 - oy + ly), with ox (oy) = 1 for an
@@ -208,22 +231,34 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   }
 
   // the staged points of one input plane (load record ld) into registers
-  auto load_window = [&](T (&v)[EPT], const int4 ld) {
+  auto load_window = [&](RW (&v)[EPT], const int4 ld) {
     const T* src = plane_at(U, ld.x, a.ps);
     const uint32_t mx = 0u - uint32_t(ld.z), my = 0u - uint32_t(ld.w);
-    if (PAIR && pfast) {
-      load_pair(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)), v[0], v[1]);
-      v[EPT - 1] = *at(src, sb[EPT - 1] + (sx[EPT - 1] & mx) + (sy[EPT - 1] & my));
+    if constexpr (PAIR && pfast) {
+      v[0] = *reinterpret_cast<const uint32_t*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+      v[EPT - 1] = load_raw(at(src, sb[EPT - 1] + (sx[EPT - 1] & mx) + (sy[EPT - 1] & my)));
     } else {
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) v[q] = *at(src, sb[q] + (sx[q] & mx) + (sy[q] & my));
+      for (int q = 0; q < EPT; ++q) v[q] = load_raw(at(src, sb[q] + (sx[q] & mx) + (sy[q] & my)));
+    }
+  };
+  // value of staged point q of a window's registers
+  auto wval = [&](const RW (&v)[EPT], int q) -> C {
+    if constexpr (sizeof(T) == 2) {
+      if constexpr (PAIR && pfast) {
+        if (q == 0) return __uint_as_float(v[0] << 16);
+        if (q == 1) return __uint_as_float(v[0] & 0xFFFF0000u);
+      }
+      return __uint_as_float(v[q] << 16);
+    } else {
+      return v[q];
     }
   };
 
   // synchronous staging of planes [b0, b1) of a load list into LDS
   auto stage_sync = [&](int first, int b0, int b1) {
     for (int bb = b0; bb < b1; bb += LB) {
-      T v[LB][EPT];
+      RW v[LB][EPT];
 #pragma unroll
       for (int b = 0; b < LB; ++b)
         if (bb + b < b1) load_window(v[b], rec4(loads, first + bb + b));
@@ -233,14 +268,15 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
           const int4 ld = rec4(loads, first + bb + b);
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
-            if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(to_c(v[b][q]));
+            if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(wval(v[b], q));
         }
       }
     }
   };
 
-  // current values of the output rows r0, r0 + NG, ... (RB of them, < r1)
-  auto load_rows = [&](C (&uv)[RB][PPT], int r0, int r1) {
+  // current values of the output rows r0, r0 + NG, ... (RB of them, < r1),
+  // raw (a pair: one word in uv[i][0])
+  auto load_rows = [&](RW (&uv)[RB][PPT], int r0, int r1) {
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
       const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
@@ -248,22 +284,25 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         cptr<int> rec = cat(rows, uint32_t(r) * 64u);
         const T* up = plane_at(U, rec[0], a.ps);
         const bool s1 = rec[1] != 0;
-        bool done = false;
-        if constexpr (PAIR) {
-          if (pfast) {  // both points of the pair lie inside the output grid along x
-            uint32_t w = 0;
-            if (s1 ? val1[0] : val0[0]) w = load_pair_stream(at(up, goff[0] * TS));
-            uv[i][0] = to_c(bf16{uint16_t(w & 0xFFFFu)});
-            uv[i][PPT - 1] = to_c(bf16{uint16_t(w >> 16)});
-            done = true;
-          }
-        }
-        if (!done) {
+        if constexpr (PAIR && pfast) {  // both points of the pair lie inside the output grid along x
+          uint32_t w = 0;
+          if (s1 ? val1[0] : val0[0]) w = load_pair_stream(at(up, goff[0] * TS));
+          uv[i][0] = w;
+        } else {
 #pragma unroll
           for (int p = 0; p < PPT; ++p)
-            uv[i][p] = (s1 ? val1[p] : val0[p]) ? to_c(load_stream(at(up, goff[p] * TS))) : C(0);
+            uv[i][p] = (s1 ? val1[p] : val0[p]) ? load_raw_stream(at(up, goff[p] * TS)) : RW(0);
         }
       }
+    }
+  };
+  // value of point p of a row's registers
+  auto rval = [&](const RW (&uv)[PPT], int p) -> C {
+    if constexpr (sizeof(T) == 2) {
+      if constexpr (PAIR && pfast) return __uint_as_float(p == 0 ? (uv[0] << 16) : (uv[0] & 0xFFFF0000u));
+      return __uint_as_float(uv[p] << 16);
+    } else {
+      return uv[p];
     }
   };
 
@@ -318,7 +357,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   // the padding couplings read this plane of zeros
   for (int e = tid; e < P; e += 256) L[a.zero_off + e] = S(0);
   // prologue: the first window and the first rows
-  C ua[RB][PPT];
+  RW ua[RB][PPT];
   {
     const int4 ord = rec4(orders, chk.x);
     stage_sync(ord.x, 0, ord.y - ord.x);
@@ -335,12 +374,12 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     const int4 nxt = has_next ? rec4(orders, o + 1) : make_int4(0, 0, 0, 0);
     const int nl = nxt.y - nxt.x;
     // 1. the next window into registers (every thread loads its own elements)
-    T stg[MAXP][EPT];
+    RW stg[MAXP][EPT];
 #pragma unroll
     for (int b = 0; b < MAXP; ++b)
       if (b < nl) load_window(stg[b], rec4(loads, nxt.x + b));
     // 2. the first output rows of the next order
-    C ub[RB][PPT];
+    RW ub[RB][PPT];
     if (has_next) {
       load_rows(ub, nxt.z + grp, nxt.w);
       prefetch_decay(nxt, nc0, nc1);
@@ -377,7 +416,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
             if (so >= 0) W += to_c(L[so + pos[p]]);
             const C c = gslot ? c1[p] : c0[p];
             const C E = gslot ? e1[p] : e0[p];
-            nv[p] = from_c<T>(sub_step(ua[i][p], W, c, E, a.tau));
+            nv[p] = from_c<T>(sub_step(rval(ua[i], p), W, c, E, a.tau));
             if (!(PAIR && pfast) && (gslot ? val1[p] : val0[p])) store_stream(at(up, goff[p] * TS), nv[p]);
           }
           if (PAIR && pfast && (gslot ? val1[0] : val0[0])) store_pair_stream(at(up, goff[0] * TS), nv[0], nv[PPT - 1]);
@@ -392,7 +431,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const int4 ld = rec4(loads, nxt.x + b);
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
-          if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(to_c(stg[b][q]));
+          if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(wval(stg[b], q));
       }
     }
     if (nl > MAXP) stage_sync(nxt.x, MAXP, nl);
@@ -406,7 +445,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) ua[i][p] = ub[i][p];
+      for (int p = 0; p < (PAIR && pfast ? 1 : PPT); ++p) ua[i][p] = ub[i][p];
   }
 }
 
@@ -420,8 +459,16 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
   // logical block = tile * nchunks + chunk: the m ranges of one tile run on
   // the same XCD, one after another, and share its L2
   using C = typename ComputeOf<T>::type;
-  sweep_tile<T, TX, TY, CAP>(U, decay, (cptr<int>)chunks, (cptr<int>)orders, (cptr<int>)loads, (cptr<int>)rows,
-                             (cptr<C>)rcoef, a, xcd_tile(blockIdx.x, gridDim.x));
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  if constexpr (kPair<T, TX, TY>) {
+    if (pair_fast<T, TX, TY>(a, lb)) {
+      sweep_tile<T, TX, TY, CAP, true>(U, decay, (cptr<int>)chunks, (cptr<int>)orders, (cptr<int>)loads,
+                                       (cptr<int>)rows, (cptr<C>)rcoef, a, lb);
+      return;
+    }
+  }
+  sweep_tile<T, TX, TY, CAP, false>(U, decay, (cptr<int>)chunks, (cptr<int>)orders, (cptr<int>)loads,
+                                    (cptr<int>)rows, (cptr<C>)rcoef, a, lb);
 }
 
 // Sweep number j of a batched run.  Instances are sorted by their number of
@@ -485,12 +532,21 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
   a.parity = par;
   a.strip = e.strip;
   a.tau = C((j == 0 || j == e.nsweeps - 1) ? e.tau_half : e.tau_full);
-  sweep_tile<T, TX, TY, CAP>((T*)(gptr<T>)e.u, (const C*)(gptr<const C>)e.decay,
-                             (cptr<int>)((gptr<const char>)e.chunks[par] + bd),
-                             (cptr<int>)((gptr<const char>)e.orders[par] + bd),
-                             (cptr<int>)((gptr<const char>)e.loads[par] + bd),
-                             (cptr<int>)((gptr<const char>)e.rows[par] + bd),
-                             (cptr<C>)((gptr<const char>)e.rcoef[par] + bd), a, item - first[lo]);
+  const int lb = item - first[lo];
+  T* const u = (T*)(gptr<T>)e.u;
+  const C* const dec = (const C*)(gptr<const C>)e.decay;
+  const cptr<int> ch = (cptr<int>)((gptr<const char>)e.chunks[par] + bd);
+  const cptr<int> od = (cptr<int>)((gptr<const char>)e.orders[par] + bd);
+  const cptr<int> ldl = (cptr<int>)((gptr<const char>)e.loads[par] + bd);
+  const cptr<int> rw = (cptr<int>)((gptr<const char>)e.rows[par] + bd);
+  const cptr<C> rc = (cptr<C>)((gptr<const char>)e.rcoef[par] + bd);
+  if constexpr (kPair<T, TX, TY>) {
+    if (pair_fast<T, TX, TY>(a, lb)) {
+      sweep_tile<T, TX, TY, CAP, true>(u, dec, ch, od, ldl, rw, rc, a, lb);
+      return;
+    }
+  }
+  sweep_tile<T, TX, TY, CAP, false>(u, dec, ch, od, ldl, rw, rc, a, lb);
 }
 
 // ------------------------------------------------------------ variants
