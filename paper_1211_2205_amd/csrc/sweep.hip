@@ -259,9 +259,14 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   auto stage_sync = [&](int first, int b0, int b1) {
     for (int bb = b0; bb < b1; bb += LB) {
       RW v[LB][EPT];
+      // the records first (clamped into the list: every scalar load is
+      // unconditional, so they issue together), then the loads they describe
+      int4 lr[LB];
+#pragma unroll
+      for (int b = 0; b < LB; ++b) lr[b] = rec4(loads, first + min(bb + b, b1 - 1));
 #pragma unroll
       for (int b = 0; b < LB; ++b)
-        if (bb + b < b1) load_window(v[b], rec4(loads, first + bb + b));
+        if (bb + b < b1) load_window(v[b], lr[b]);
 #pragma unroll
       for (int b = 0; b < LB; ++b) {
         if (bb + b < b1) {
@@ -277,13 +282,22 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   // current values of the output rows r0, r0 + NG, ... (RB of them, < r1),
   // raw (a pair: one word in uv[i][0])
   auto load_rows = [&](RW (&uv)[RB][PPT], int r0, int r1) {
+    // plane and grid slot of every row first (row indices clamped into the
+    // table: unconditional scalar loads that issue together), then the loads
+    int rk[RB], rs[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int r = __builtin_amdgcn_readfirstlane(max(min(r0 + NG * i, r1 - 1), 0));
+      const cptr<int> rec = cat(rows, uint32_t(r) * 64u);
+      rk[i] = rec[0];
+      rs[i] = rec[1];
+    }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
       const int r = __builtin_amdgcn_readfirstlane(r0 + NG * i);
       if (r < r1) {
-        cptr<int> rec = cat(rows, uint32_t(r) * 64u);
-        const T* up = plane_at(U, rec[0], a.ps);
-        const bool s1 = rec[1] != 0;
+        const T* up = plane_at(U, rk[i], a.ps);
+        const bool s1 = rs[i] != 0;
         if constexpr (PAIR && pfast) {  // both points of the pair lie inside the output grid along x
           uint32_t w = 0;
           if (s1 ? val1[0] : val0[0]) w = load_pair_stream(at(up, goff[0] * TS));
@@ -375,9 +389,16 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     const int nl = nxt.y - nxt.x;
     // 1. the next window into registers (every thread loads its own elements)
     RW stg[MAXP][EPT];
+    {
+      // the records first (clamped into the list: unconditional scalar loads
+      // that issue together), then the loads they describe
+      int4 nrec[MAXP];
 #pragma unroll
-    for (int b = 0; b < MAXP; ++b)
-      if (b < nl) load_window(stg[b], rec4(loads, nxt.x + b));
+      for (int b = 0; b < MAXP; ++b) nrec[b] = rec4(loads, nxt.x + max(min(b, nl - 1), 0));
+#pragma unroll
+      for (int b = 0; b < MAXP; ++b)
+        if (b < nl) load_window(stg[b], nrec[b]);
+    }
     // 2. the first output rows of the next order
     RW ub[RB][PPT];
     if (has_next) {
