@@ -501,7 +501,10 @@ int starmap_batch_last_run(const starmap_batch* b, double* ms, int64_t* updates,
    the most cell-moment work (-1 and 0 before the first device call).
    starmap_batch_autotune times, for each group on its own, every pair that
    fits on a few sweeps with sub-step length 0 (state unchanged) and keeps the
-   group's fastest. */
+   group's fastest; then it times the whole batch with those tiles as
+   concurrent chains against merged launches on the two most promising
+   common variants (each group at its fastest width for that variant) and
+   keeps the fastest configuration. */
 int starmap_batch_set_variant(starmap_batch* b, int32_t variant, int32_t width);
 int starmap_batch_get_variant(const starmap_batch* b, int32_t* variant, int32_t* width);
 int starmap_batch_autotune(starmap_batch* b, int32_t sweeps_per_variant);
@@ -515,8 +518,19 @@ int starmap_batch_get_group(const starmap_batch* b, int32_t group, int32_t* N, i
                             int32_t* width);
 
 /* Tile variant and m-range width of one group only (errors as
-   starmap_batch_set_variant; STARMAP_EINVAL for a group out of range). */
+   starmap_batch_set_variant; STARMAP_EINVAL for a group out of range).
+   Giving one group another variant than the others turns merged launches
+   off. */
 int starmap_batch_set_group_variant(starmap_batch* b, int32_t group, int32_t variant, int32_t width);
+
+/* Merged launches: merged != 0 runs every sweep as ONE launch over the
+   running instances of all groups (the groups keep their m-range widths but
+   must share one tile variant, else STARMAP_EINVAL); 0 (the default) runs one
+   launch per group as concurrent chains.  starmap_batch_autotune chooses
+   between the two by timing sweeps of the whole batch.  get returns 0 or 1
+   (or a negative error code).  Results are the same bits either way. */
+int starmap_batch_set_merged(starmap_batch* b, int32_t merged);
+int starmap_batch_get_merged(const starmap_batch* b);
 
 const char* starmap_last_error(void);
 

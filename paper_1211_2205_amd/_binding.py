@@ -118,6 +118,8 @@ SIGNATURES = [
     ("starmap_batch_get_variant", [_vp, _i32p, _i32p], ctypes.c_int),
     ("starmap_batch_autotune", [_vp, ctypes.c_int32], ctypes.c_int),
     ("starmap_batch_group_count", [_vp], ctypes.c_int),
+    ("starmap_batch_set_merged", [_vp, ctypes.c_int32], ctypes.c_int),
+    ("starmap_batch_get_merged", [_vp], ctypes.c_int),
     ("starmap_batch_set_group_variant", [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     ("starmap_batch_get_group", [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p], ctypes.c_int),
     ("starmap_last_error", [], ctypes.c_char_p),

@@ -1762,15 +1762,20 @@ namespace starmap {
 namespace detail {
 struct BatchGroup {
   int N = 0;
-  std::vector<int> members;   // instance indices, in the caller's order
+  std::vector<int> members;  // instance indices, in the caller's order
   int variant = -1, width = 0, slots = 0;
   bool tiles_set = false;
-  // launch plan of the current table
-  std::vector<int> order;     // members with sweeps left, by sweeps (descending, stable)
+};
+// One launch per sweep over the running instances of a plan: a group, or with
+// merged launches every instance (one tile variant for all groups).
+struct BatchPlan {
+  int variant = 0, slots = 0;
+  std::vector<int> members;  // instances the plan covers
+  std::vector<int> order;    // members with sweeps left, by sweeps (descending, stable)
   std::vector<int> nsweeps;
-  std::vector<int> first;     // workgroup prefix (order.size() + 1 values)
-  size_t tab0 = 0;            // first table entry of the group
-  size_t first0 = 0;          // first prefix value of the group in the table's int array
+  std::vector<int> first;    // workgroup prefix (order.size() + 1 values)
+  size_t tab0 = 0;           // first table entry of the plan
+  size_t first0 = 0;         // first prefix value of the plan in the table's int array
 };
 }  // namespace detail
 }  // namespace starmap
@@ -1779,6 +1784,11 @@ struct starmap_batch {
   std::vector<starmap_solver*> inst;  // as given by the caller
   int storage = STORE_FP64;
   std::vector<starmap::detail::BatchGroup> groups;  // by ascending N
+  // merged: one launch per sweep over the instances of every group (all
+  // groups on one tile variant); else one launch per sweep and group, each
+  // group's launches a chain on its own stream
+  bool merged = false;
+  std::vector<starmap::detail::BatchPlan> plans;  // of the current table
   hipStream_t stream = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   // one stream per group: a run forks from `stream` into the groups' chains
@@ -1893,15 +1903,35 @@ int items_of(const starmap_solver* s) {
   return ntx * nty * int(s->prog[0].chunks.size());
 }
 
-// Per group, the entries of the members with sweeps[i] > 0 sorted by sweeps
-// (descending, stable), uploaded with the group's workgroup prefix.
+// Per launch plan, the entries of the members with sweeps[i] > 0 sorted by
+// sweeps (descending, stable), uploaded with the plan's workgroup prefix.
 // zero_tau: every sub-step length 0 (timing on live state leaves it unchanged).
 int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau) {
   const int count = int(b->inst.size());
   const int ng = int(b->groups.size());
+  b->plans.clear();
+  if (b->merged && ng > 1) {
+    BatchPlan pl;
+    pl.variant = b->groups[0].variant;
+    for (const auto& g : b->groups) {
+      if (g.variant != pl.variant) return fail(STARMAP_ESTATE, "merged batch launches need one tile variant");
+      pl.slots = std::max(pl.slots, g.slots);
+      pl.members.insert(pl.members.end(), g.members.begin(), g.members.end());
+    }
+    b->plans.push_back(pl);
+  } else {
+    for (const auto& g : b->groups) {
+      BatchPlan pl;
+      pl.variant = g.variant;
+      pl.slots = g.slots;
+      pl.members = g.members;
+      b->plans.push_back(pl);
+    }
+  }
+  if (b->merged && ng > 1) HIP_TRY(prepare_sweep(b->storage, b->plans[0].variant, b->plans[0].slots));
   std::vector<BatchEntry> tab;
   std::vector<int> firsts;
-  for (auto& g : b->groups) {
+  for (auto& g : b->plans) {
     std::vector<int> ord;
     for (int i : g.members)
       if (sweeps[i] > 0) ord.push_back(i);
@@ -1963,7 +1993,7 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
   HIP_TRY(hipMemcpyAsync(b->dtab, buf.data(), buf.size(), hipMemcpyHostToDevice, b->stream));
   if (b->closure) {
     // the closure sweep's instances in the (single) group's order, with their block prefix
-    const BatchGroup& g = b->groups[0];
+    const BatchPlan& g = b->plans[0];
     std::vector<ClosureInst> ct(g.order.size());
     std::vector<int> cf(g.order.size() + 1, 0);
     int64_t nb = 0;
@@ -1997,7 +2027,7 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
 }
 
 // Queue sweeps j0 .. j1-1 of the current table on the batch stream: one
-// launch per group with instances still running (only group `only` if >= 0).
+// launch per plan with instances still running (only plan `only` if >= 0).
 int batch_launch(starmap_batch* b, int j0, int j1, int only = -1) {
   const BatchEntry* tab = reinterpret_cast<const BatchEntry*>(b->dtab);
   const int* firsts =
@@ -2005,7 +2035,7 @@ int batch_launch(starmap_batch* b, int j0, int j1, int only = -1) {
   for (int j = j0; j < j1; ++j) {
     if (b->closure && (j & 1) == 0) {
       // odd sweep of closure solvers: the network and the odd update in one kernel
-      const BatchGroup& g = b->groups[0];
+      const BatchPlan& g = b->plans[0];
       int na = int(g.nsweeps.size());
       while (na > 0 && g.nsweeps[na - 1] <= j) --na;
       if (na == 0) continue;
@@ -2017,9 +2047,9 @@ int batch_launch(starmap_batch* b, int j0, int j1, int only = -1) {
                                    reinterpret_cast<const ClosureNet*>(dptr(s0, s0->off_net)), b->stream));
       continue;
     }
-    for (int gi = 0; gi < int(b->groups.size()); ++gi) {
+    for (int gi = 0; gi < int(b->plans.size()); ++gi) {
       if (only >= 0 && gi != only) continue;
-      const BatchGroup& g = b->groups[gi];
+      const BatchPlan& g = b->plans[gi];
       int na = int(g.nsweeps.size());
       while (na > 0 && g.nsweeps[na - 1] <= j) --na;
       if (na == 0) continue;
@@ -2041,35 +2071,45 @@ double group_work(const starmap_batch* b, const BatchGroup& g) {
   return w;
 }
 
-// Every sweep of a run: a single group (or a closure batch) on the batch
-// stream; several groups each as its own chain on its own stream, forked from
-// and joined back into the batch stream, so that one group's launches fill
-// the machine while another's drain.
-int batch_launch_all(starmap_batch* b, int jmax) {
-  if (b->closure || b->groups.size() == 1) return batch_launch(b, 0, jmax);
+// Cell-moment work of a plan's members for a whole run.
+double plan_work(const starmap_batch* b, const BatchPlan& g) {
+  double w = 0.0;
+  for (int i : g.members) {
+    const starmap_solver* s = b->inst[i];
+    w += double(s->nmom) * s->nx * s->ny * double(s->steps_total);
+  }
+  return w;
+}
+
+// Sweeps j0 .. j1-1 of the current table: a single plan (or a closure batch)
+// on the batch stream; several plans each as a chain on its own stream, forked
+// from and joined back into the batch stream, so that one group's launches
+// fill the machine while another's drain.
+int batch_launch_all(starmap_batch* b, int j0, int j1) {
+  if (b->closure || b->plans.size() == 1) return batch_launch(b, j0, j1);
   const BatchEntry* tab = reinterpret_cast<const BatchEntry*>(b->dtab);
   const int* firsts =
       reinterpret_cast<const int*>(static_cast<char*>(b->dtab) + align256(b->inst.size() * sizeof(BatchEntry)));
-  // the groups with the most work first: the chains start one after another
+  // the plans with the most work first: the chains start one after another
   // as the machine frees up, and the longest one bounds the run
-  std::vector<int> ord(b->groups.size());
+  std::vector<int> ord(b->plans.size());
   for (size_t gi = 0; gi < ord.size(); ++gi) ord[gi] = int(gi);
   std::stable_sort(ord.begin(), ord.end(),
-                   [&](int x, int y) { return group_work(b, b->groups[x]) > group_work(b, b->groups[y]); });
+                   [&](int x, int y) { return plan_work(b, b->plans[x]) > plan_work(b, b->plans[y]); });
   HIP_TRY(hipEventRecord(b->fork, b->stream));
   for (int gi : ord) HIP_TRY(hipStreamWaitEvent(b->gstream[gi], b->fork, 0));
-  // submitted sweep by sweep across the groups (a chain submitted whole could
+  // submitted sweep by sweep across the plans (a chain submitted whole could
   // fill its queue and hold back the next)
-  for (int j = 0; j < jmax; ++j)
+  for (int j = j0; j < j1; ++j)
     for (int gi : ord) {
-      const BatchGroup& g = b->groups[gi];
+      const BatchPlan& g = b->plans[gi];
       int na = int(g.nsweeps.size());
       while (na > 0 && g.nsweeps[na - 1] <= j) --na;
       if (na == 0) continue;
       HIP_TRY(launch_sweep_batch(b->storage, g.variant, tab + g.tab0, firsts + g.first0, na, g.first[na], j,
                                  g.slots, b->gstream[gi]));
     }
-  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+  for (size_t gi = 0; gi < b->plans.size(); ++gi) {
     HIP_TRY(hipEventRecord(b->gdone[gi], b->gstream[gi]));
     HIP_TRY(hipStreamWaitEvent(b->stream, b->gdone[gi], 0));
   }
@@ -2177,6 +2217,10 @@ int starmap_batch_set_group_variant(starmap_batch* b, int32_t group, int32_t var
   if (variant < 0 || variant >= sweep_variant_count()) return fail(STARMAP_EINVAL, "unknown variant");
   if (std::find(std::begin(kChunkWidths), std::end(kChunkWidths), width) == std::end(kChunkWidths))
     return fail(STARMAP_EINVAL, "unsupported m-range width");
+  int rc = batch_ready(b);
+  if (rc) return rc;
+  // merged launches stay on while every group keeps one variant
+  if (b->merged && b->groups.size() > 1 && variant != b->groups[group == 0 ? 1 : 0].variant) b->merged = false;
   return group_prepare(b, b->groups[group], variant, width);
 }
 
@@ -2236,26 +2280,29 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
   if (rc) return rc;
   int jmax = 0;
   int64_t launches = 0;
-  for (const auto& g : b->groups) {
+  for (const auto& g : b->plans) {
     if (!g.nsweeps.empty()) jmax = std::max(jmax, g.nsweeps[0]);
     for (int j = 0; !g.nsweeps.empty() && j < g.nsweeps[0]; ++j)
       if (!(b->closure && (j & 1) == 0)) ++launches;
   }
-  if (b->closure && !b->groups[0].nsweeps.empty()) launches += (b->groups[0].nsweeps[0] + 1) / 2;
+  if (b->closure && !b->plans[0].nsweeps.empty()) launches += (b->plans[0].nsweeps[0] + 1) / 2;
   HIP_TRY(hipEventRecord(b->ev[0], b->stream));
   if (jmax > 0) {
     if (use_graph) {
-      // the graph depends on every group's tile (kernel, LDS) and launch plan
-      std::vector<int> key;
-      for (const auto& g : b->groups) {
-        key.insert(key.end(), {g.variant, g.width, g.slots, int(g.nsweeps.size())});
+      // the graph depends on every group's tile (kernel, LDS, programs) and
+      // on the launch plans
+      std::vector<int> key{b->merged ? 1 : 0};
+      for (const auto& g : b->groups) key.insert(key.end(), {g.variant, g.width, g.slots});
+      for (const auto& g : b->plans) {
+        key.insert(key.end(), {g.variant, g.slots, int(g.nsweeps.size())});
+        key.insert(key.end(), g.order.begin(), g.order.end());
         key.insert(key.end(), g.nsweeps.begin(), g.nsweeps.end());
         key.insert(key.end(), g.first.begin(), g.first.end());
       }
       if (!b->exec || key != b->graph_key) {
         drop_graph(b);
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        rc = batch_launch_all(b, jmax);
+        rc = batch_launch_all(b, 0, jmax);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b->stream, &g);
         if (rc) {
@@ -2271,7 +2318,7 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
       }
       HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     } else {
-      rc = batch_launch_all(b, jmax);
+      rc = batch_launch_all(b, 0, jmax);
       if (rc) return rc;
     }
   }
@@ -2280,7 +2327,7 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
   if (b->closure) {
-    const BatchGroup& g = b->groups[0];
+    const BatchPlan& g = b->plans[0];
     for (size_t r = 0; r < g.order.size(); ++r) {
       starmap_solver* s = b->inst[g.order[r]];
       // (nsweeps + 1) / 2 odd sweeps each moved the order-5 moments once
@@ -2314,14 +2361,18 @@ int starmap_batch_autotune(starmap_batch* b, int32_t sweeps) {
   if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
   if (sweeps < 1) sweeps = 1;
   const int count = int(b->inst.size());
+  const int ng = int(b->groups.size());
   const int max_lds = max_lds_bytes();
   {
     int rc = batch_ready(b);
     if (rc) return rc;
   }
+  const bool verbose = std::getenv("STARMAP_VERBOSE") != nullptr;
+  b->merged = false;
   // each group on its own: every (width, variant) pair that fits, timed on a
   // sweep pair of the group's instances (tau = 0 leaves every value unchanged)
-  for (int gi = 0; gi < int(b->groups.size()); ++gi) {
+  std::vector<std::map<std::pair<int, int>, float>> times(ng);
+  for (int gi = 0; gi < ng; ++gi) {
     BatchGroup& g = b->groups[gi];
     int best_v = -1, best_w = 0;
     float best_ms = 0.f;
@@ -2359,10 +2410,12 @@ int starmap_batch_autotune(starmap_batch* b, int32_t sweeps) {
         HIP_TRY(hipEventSynchronize(b->ev[1]));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
-        if (std::getenv("STARMAP_VERBOSE")) {
+        ms /= float(sweeps);
+        times[gi][{v, w}] = ms;
+        if (verbose) {
           const TileShape ts = sweep_variant(v);
           std::fprintf(stderr, "starmap batch autotune: N %d width %d variant %d (%dx%d) %.3f ms per sweep pair\n",
-                       g.N, w, v, ts.tx, ts.ty, ms / sweeps);
+                       g.N, w, v, ts.tx, ts.ty, ms);
         }
         if (best_v < 0 || ms < best_ms) {
           best_v = v;
@@ -2375,7 +2428,100 @@ int starmap_batch_autotune(starmap_batch* b, int32_t sweeps) {
     int rc = group_prepare(b, g, best_v, best_w);
     if (rc) return rc;
   }
+  if (b->closure || ng == 1) return STARMAP_OK;
+
+  // the whole batch: the groups' best tiles as concurrent chains, against
+  // merged launches on one variant (each group at its best width for it),
+  // each timed on sweep pairs of every instance
+  auto time_all = [&](float* out) -> int {
+    int rc = batch_table(b, std::vector<int>(count, 3), true);
+    if (!rc) rc = batch_launch_all(b, 1, 3);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+    for (int i = 0; i < sweeps && !rc; ++i) rc = batch_launch_all(b, 1, 3);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b->ev[1], b->stream));
+    HIP_TRY(hipEventSynchronize(b->ev[1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+    *out = ms / float(sweeps);
+    return STARMAP_OK;
+  };
+  std::vector<std::pair<int, int>> chains(ng);
+  for (int gi = 0; gi < ng; ++gi) chains[gi] = {b->groups[gi].variant, b->groups[gi].width};
+  float best_ms = 0.f;
+  int rc = time_all(&best_ms);
+  if (rc) return rc;
+  if (verbose) std::fprintf(stderr, "starmap batch autotune: groups as chains %.3f ms per sweep pair\n", best_ms);
+  int best_merged_v = -1;
+  // candidate variants: timed for every group, ranked by the sum of the
+  // groups' best times on them
+  std::vector<std::pair<float, int>> cand;
+  for (int v = 0; v < sweep_variant_count(); ++v) {
+    float sum = 0.f;
+    bool all = true;
+    for (int gi = 0; gi < ng && all; ++gi) {
+      float bv = -1.f;
+      for (const auto& kv : times[gi])
+        if (kv.first.first == v && (bv < 0.f || kv.second < bv)) bv = kv.second;
+      if (bv < 0.f) all = false; else sum += bv;
+    }
+    if (all) cand.push_back({sum, v});
+  }
+  std::sort(cand.begin(), cand.end());
+  if (cand.size() > 2) cand.resize(2);
+  std::vector<int> best_widths;
+  for (const auto& c : cand) {
+    const int v = c.second;
+    std::vector<int> widths(ng);
+    for (int gi = 0; gi < ng; ++gi) {
+      float bv = -1.f;
+      for (const auto& kv : times[gi])
+        if (kv.first.first == v && (bv < 0.f || kv.second < bv)) {
+          bv = kv.second;
+          widths[gi] = kv.first.second;
+        }
+      rc = group_prepare(b, b->groups[gi], v, widths[gi]);
+      if (rc) return rc;
+    }
+    b->merged = true;
+    float ms = 0.f;
+    rc = time_all(&ms);
+    b->merged = false;
+    if (rc) return rc;
+    if (verbose) std::fprintf(stderr, "starmap batch autotune: merged on variant %d %.3f ms per sweep pair\n", v, ms);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_merged_v = v;
+      best_widths = widths;
+    }
+  }
+  for (int gi = 0; gi < ng; ++gi) {
+    rc = best_merged_v >= 0 ? group_prepare(b, b->groups[gi], best_merged_v, best_widths[gi])
+                            : group_prepare(b, b->groups[gi], chains[gi].first, chains[gi].second);
+    if (rc) return rc;
+  }
+  b->merged = best_merged_v >= 0;
+  drop_graph(b);
   return STARMAP_OK;
+}
+
+int starmap_batch_set_merged(starmap_batch* b, int32_t merged) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  int rc = batch_ready(b);
+  if (rc) return rc;
+  if (merged)
+    for (const auto& g : b->groups)
+      if (g.variant != b->groups[0].variant)
+        return fail(STARMAP_EINVAL, "merged batch launches need one tile variant for every group");
+  b->merged = merged != 0;
+  drop_graph(b);
+  return STARMAP_OK;
+}
+
+int starmap_batch_get_merged(const starmap_batch* b) {
+  if (!b) return fail(STARMAP_EINVAL, "batch is NULL");
+  return b->merged ? 1 : 0;
 }
 
 }  // extern "C"

@@ -459,6 +459,13 @@ class Batch:
             out.append({"N": N.value, "count": c.value, "variant": v.value, "width": w.value})
         return out
 
+    def set_merged(self, merged):
+        """One launch per sweep over every group (shared tile variant) or not."""
+        B.check(B.lib().starmap_batch_set_merged(self._h, 1 if merged else 0))
+
+    def merged(self):
+        return bool(B.check(B.lib().starmap_batch_get_merged(self._h)))
+
     def set_group_variant(self, group, variant, width):
         B.check(B.lib().starmap_batch_set_group_variant(self._h, int(group), int(variant), int(width)))
 

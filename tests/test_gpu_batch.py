@@ -148,6 +148,56 @@ def test_batch_groups_with_their_own_tiles(monkeypatch):
     b.close()
 
 
+def test_merged_launches_equal_chains_and_single_runs(monkeypatch):
+    """Merged launches (one launch per sweep over every group, one variant,
+    each group its own m-range width) give the same bits as the per-group
+    chains and as the single runs; graph and eager, and a relaunched graph."""
+    probs = _mixed()
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    widths = [4, 6, 8]
+    for gi, g in enumerate(b.groups()):
+        b.set_group_variant(gi, 11, widths[gi % 3])
+    tiles = {g["N"]: (g["variant"], g["width"]) for g in b.groups()}
+    b.run()
+    chains = [s.moments() for s in solvers]
+    b.set_merged(True)
+    assert b.merged()
+    launches = []
+    for use_graph in (True, True, False):
+        b.reset()
+        rec = b.run(use_graph=use_graph)
+        launches.append(rec["launches"])
+        for p, s, c in zip(probs, solvers, chains):
+            assert _identical(s.moments(), c), (p.name, use_graph)
+    # one launch per sweep in total, for as long as the longest instance runs
+    assert launches[0] == 2 * max(s.nsteps for s in solvers) + 1
+    for p, c in zip(probs, chains):
+        assert _identical(c, _single(p, *tiles[p.N], monkeypatch)), p.name
+    # a group on another variant turns merging off; merging needs one variant
+    b.set_group_variant(0, 0, 8)
+    assert not b.merged()
+    with pytest.raises(pa.StarmapError):
+        b.set_merged(True)
+    b.close()
+
+
+def test_batch_autotune_choice_is_consistent():
+    """After the autotuner, merged launches imply one variant for all groups,
+    and the run equals the oracle."""
+    probs = _mixed("fp32")
+    solvers = [pa.Solver.from_problem(p) for p in probs]
+    b = pa.Batch(solvers)
+    b.autotune(1)
+    groups = b.groups()
+    if b.merged():
+        assert len({g["variant"] for g in groups}) == 1
+    b.run()
+    for p, s in zip(probs[:3], solvers[:3]):
+        assert_parity(s.moments(), run_oracle(p).u, 1e-5, p.name)
+    b.close()
+
+
 def test_batch_rejects_bad_input():
     a = pa.Solver.from_problem(_mixed()[0])
     c = pa.Solver.from_problem(_mixed("fp32")[1])
