@@ -256,7 +256,12 @@ int starmap_diagnostics_noalloc(const starmap_solver* s, double* mass_r00, doubl
    m-range width (4, 6, 8), on a few sweeps of this solver, keeps the fastest
    pair and writes it to the cache file named by the environment variable
    STARMAP_TUNE_CACHE (if set).  Variants are 0 .. starmap_variant_count()-1;
-   another value fails with STARMAP_EINVAL. */
+   another value fails with STARMAP_EINVAL.  The environment variable
+   STARMAP_TILE_STRIP (read by starmap_create) sets
+   the order in which workgroups take the tiles: k >= 2 strips of k tile
+   rows taken column by column (default 8), k <= -2 strips of -k tile
+   columns taken row by row, otherwise row by row; every order gives the
+   same bits. */
 int starmap_variant_count(void);
 int starmap_set_variant(starmap_solver* s, int32_t variant);
 int starmap_get_variant(const starmap_solver* s, int32_t* variant, int32_t* tile_x, int32_t* tile_y);

@@ -1071,7 +1071,10 @@ int starmap_create(const starmap_problem* prob, starmap_solver** out) {
   s->pitch = int((s->nx + 1 + 63) / 64 * 64);
   s->nrows = s->ny + 1;
   s->plane_stride = (int64_t(s->pitch) * s->nrows + 127) / 128 * 128;
-  if (const char* e = std::getenv("STARMAP_TILE_STRIP")) s->tile_strip = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("STARMAP_TILE_STRIP")) {
+    const int v = std::atoi(e);
+    s->tile_strip = (v >= 2 || v <= -2) ? v : 1;
+  }
   // The kernels address a plane with 32-bit byte offsets (element offset
   // times the storage or compute size, whichever is larger): keep every such
   // offset below 2^31.

@@ -86,19 +86,32 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   return start + idx;
 }
 
-// Tile number t -> tile column and row.  Tiles are numbered in strips of
-// `strip` tile rows, and within a strip column by column: consecutive tiles
-// are vertical neighbours (they share a halo row) and horizontal neighbours
-// are `strip` tiles apart, so with the XCD-contiguous block order both halos
-// of a tile are read while its neighbours' are still in that XCD's L2.
-// strip <= 1 numbers the tiles row by row.
+// Tile number t -> tile column and row.  strip >= 2: tiles are numbered in
+// strips of `strip` tile rows, and within a strip column by column:
+// consecutive tiles are vertical neighbours (they share a halo row) and
+// horizontal neighbours are `strip` tiles apart.  strip <= -2: strips of
+// -strip tile columns, row by row within a strip: consecutive tiles are
+// horizontal neighbours (they share a halo column) and vertical neighbours
+// are -strip tiles apart.  Otherwise the tiles are numbered row by row.
+// With the XCD-contiguous block order, tiles a few numbers apart run at
+// nearly the same time on one XCD and can share halo lines in its L2.
 __device__ __forceinline__ int2 tile_xy(int t, int ntx, int nty, int strip) {
-  if (strip <= 1) return make_int2(t % ntx, t / ntx);
-  const int band = t / (strip * ntx);
-  const int row0 = band * strip;
-  const int rows = min(strip, nty - row0);
-  const int r = t - band * strip * ntx;
-  return make_int2(r / rows, row0 + r % rows);
+  if (strip >= 2) {
+    const int band = t / (strip * ntx);
+    const int row0 = band * strip;
+    const int rows = min(strip, nty - row0);
+    const int r = t - band * strip * ntx;
+    return make_int2(r / rows, row0 + r % rows);
+  }
+  if (strip <= -2) {
+    const int w = -strip;
+    const int band = t / (w * nty);
+    const int col0 = band * w;
+    const int cols = min(w, ntx - col0);
+    const int r = t - band * w * nty;
+    return make_int2(col0 + r % cols, r / cols);
+  }
+  return make_int2(t % ntx, t / ntx);
 }
 
 // Kernel tables (sweep programs, coupling records) are read-only during a

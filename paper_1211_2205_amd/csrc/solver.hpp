@@ -112,7 +112,7 @@ struct starmap_solver {
   int slots = 0;
   int nchunks = 1;               // m ranges per tile (workgroups per tile and sweep)
   int chunk_width = 0;           // m indices per range (0: default)
-  int tile_strip = 8;            // tile rows per strip of the sweep's tile order
+  int tile_strip = 8;            // tile order of the sweep: strips of k tile rows (k >= 2) or -k columns (k <= -2)
   starmap::SweepProgram prog[2];
   bool prog_uploaded = false;
 
