@@ -231,16 +231,20 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   }
 
   // the staged points of one input plane (load record ld) into registers
+  // Only the waves holding halo threads (t < TX + TY) load halo points: the
+  // others skip that load instruction (a wave-uniform branch), its value
+  // would never reach the LDS.
+  const bool halo_wave = __builtin_amdgcn_readfirstlane(tid >> 6) * 64 < TX + TY;
   auto load_window = [&](RW (&v)[EPT], const int4 ld) {
     const T* src = plane_at(U, ld.x, a.ps);
     const uint32_t mx = 0u - uint32_t(ld.z), my = 0u - uint32_t(ld.w);
     if constexpr (PAIR && pfast) {
       v[0] = *reinterpret_cast<const uint32_t*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
-      v[EPT - 1] = load_raw(at(src, sb[EPT - 1] + (sx[EPT - 1] & mx) + (sy[EPT - 1] & my)));
     } else {
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) v[q] = load_raw(at(src, sb[q] + (sx[q] & mx) + (sy[q] & my)));
+      for (int q = 0; q < PPT; ++q) v[q] = load_raw(at(src, sb[q] + (sx[q] & mx) + (sy[q] & my)));
     }
+    if (halo_wave) v[EPT - 1] = load_raw(at(src, sb[EPT - 1] + (sx[EPT - 1] & mx) + (sy[EPT - 1] & my)));
   };
   // value of staged point q of a window's registers
   auto wval = [&](const RW (&v)[EPT], int q) -> C {
