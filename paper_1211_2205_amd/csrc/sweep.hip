@@ -95,12 +95,19 @@ constexpr int kWaitVm0 = 0x0F70;
 // would move half the bytes per instruction.
 template <typename T, int TX, int TY>
 constexpr bool kPair = sizeof(T) == 2 && TX * TY == 512;
+// FP64 and FP32 on tiles of 256 points whose halo fits 128 threads: the
+// window is staged by two halves of the workgroup, each half taking every
+// other plane, each thread two x-adjacent points of it with one 16-byte
+// (8-byte) load where the pair lies inside the grid: half as many vector
+// memory instructions per staged plane as one point per thread.
+template <typename T, int TX, int TY>
+constexpr bool kWide = sizeof(T) >= 4 && TX * TY == 256 && TX + TY <= 128 && TX % 2 == 0;
 
 // Whether work item lb lies on a tile whose pairs all lie inside the grid
 // along x (FAST = true below); uniform over the workgroup.
 template <typename T, int TX, int TY, typename C>
 __device__ __forceinline__ bool pair_fast(const SweepScalars<C>& a, int lb) {
-  if constexpr (!kPair<T, TX, TY>) {
+  if constexpr (!kPair<T, TX, TY> && !kWide<T, TX, TY>) {
     return false;
   } else {
     const int2 txy = tile_xy(lb / a.nchunks, a.ntx, a.nty, a.strip);
@@ -133,9 +140,13 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   constexpr int MAXP = CAP;
   constexpr int RB = CAP - 2;  // an m range of width w has w rows and w + 2 staged planes per order
   constexpr int LB = sizeof(T) >= 8 ? 8 : 16;  // planes per batch of the synchronous staging
-  constexpr int EPT = PPT + 1;                 // staged points per thread and plane: interior + halo
   constexpr bool PAIR = kPair<T, TX, TY>;
-  static_assert(PAIR || !FAST, "the pair path is for BF16 tiles of 512 points");
+  constexpr bool WIDE = kWide<T, TX, TY>;
+  static_assert(PAIR || WIDE || !FAST, "the pair paths are for BF16 tiles of 512 points and wide staging");
+  constexpr int SE = WIDE ? 2 : PPT;    // staged interior points per thread and plane
+  constexpr int EPT = SE + 1;           // staged points per thread and plane: interior + halo
+  constexpr int SP = WIDE ? 2 : 1;      // thread halves that take turns in the planes of a window
+  static_assert(MAXP % SP == 0 && LB % SP == 0, "planes split evenly over the thread halves");
   // BF16 values travel from memory to their first use as raw bit patterns
   // (16 bits in the low half of a register, or a pair as one 32-bit word):
   // widening them right after the load would be an immediate use of the load,
@@ -143,6 +154,10 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   using RW = std::conditional_t<sizeof(T) == 2, uint32_t, T>;
 
   const int tid = threadIdx.x;
+  // staging thread index and half (WIDE: threads 0-127 stage planes 0, 2, ...
+  // of a window, threads 128-255 planes 1, 3, ...)
+  const int st = WIDE ? (tid & 127) : tid;
+  const int half = WIDE ? __builtin_amdgcn_readfirstlane(tid >> 7) : 0;
   const int tile = lb / a.nchunks;
   const int4 chk = rec4(chunks, lb - tile * a.nchunks);
   if (chk.x >= chk.y) return;  // no output rows in this m range
@@ -168,8 +183,8 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   constexpr uint32_t TS = sizeof(T);
   bool sv[EPT];
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const int e = PAIR ? 2 * tid + p : tid + p * 256;
+  for (int p = 0; p < SE; ++p) {
+    const int e = (PAIR || WIDE) ? 2 * st + p : tid + p * 256;
     const int tx = e % TX, ty = e / TX;
     const int xn = map_axis(x0 + tx, a.nx, a.px, 0), xc = map_axis(x0 + tx, a.nx, a.px, 1);
     const int yn = map_axis(y0 + ty, a.ny, a.py, 0), yc = map_axis(y0 + ty, a.ny, a.py, 1);
@@ -182,10 +197,10 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     sv[p] = true;
   }
   {
-    constexpr int h = PPT;
-    sv[h] = tid < TY + TX;
-    if (tid < TY) {  // halo column, row i
-      const int i = tid;
+    constexpr int h = SE;
+    sv[h] = st < TY + TX;
+    if (st < TY) {  // halo column, row i
+      const int i = st;
       const int xn = map_axis(x0 + TX, a.nx, a.px, 0), xc = map_axis(x0 - 1, a.nx, a.px, 1);
       const int yn = map_axis(y0 + i, a.ny, a.py, 0), yc = map_axis(y0 + i, a.ny, a.py, 1);
       sb[h] = uint32_t(yn * a.pitch + xn) * TS;
@@ -195,7 +210,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       ddx[h] = -TX;
       ddy[h] = LW;
     } else {  // halo row, column j (lanes past the halo keep in-bounds values)
-      const int j = tid < TY + TX ? tid - TY : 0;
+      const int j = st < TY + TX ? st - TY : 0;
       const int xn = map_axis(x0 + j, a.nx, a.px, 0), xc = map_axis(x0 + j, a.nx, a.px, 1);
       const int yn = map_axis(y0 + TY, a.ny, a.py, 0), yc = map_axis(y0 - 1, a.ny, a.py, 1);
       sb[h] = uint32_t(yn * a.pitch + xn) * TS;
@@ -234,15 +249,22 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   // Only the waves holding halo threads (t < TX + TY) load halo points: the
   // others skip that load instruction (a wave-uniform branch), its value
   // would never reach the LDS.
-  const bool halo_wave = __builtin_amdgcn_readfirstlane(tid >> 6) * 64 < TX + TY;
+  const bool halo_wave = __builtin_amdgcn_readfirstlane(st >> 6) * 64 < TX + TY;
   auto load_window = [&](RW (&v)[EPT], const int4 ld) {
     const T* src = plane_at(U, ld.x, a.ps);
     const uint32_t mx = 0u - uint32_t(ld.z), my = 0u - uint32_t(ld.w);
     if constexpr (PAIR && pfast) {
       v[0] = *reinterpret_cast<const uint32_t*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+    } else if constexpr (WIDE && pfast) {
+      // the pair is contiguous and aligned to its size (even x, pitch and
+      // plane stride multiples of 64 elements)
+      using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
+      const T2 w = *reinterpret_cast<const T2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+      v[0] = w.x;
+      v[1] = w.y;
     } else {
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) v[q] = load_raw(at(src, sb[q] + (sx[q] & mx) + (sy[q] & my)));
+      for (int q = 0; q < SE; ++q) v[q] = load_raw(at(src, sb[q] + (sx[q] & mx) + (sy[q] & my)));
     }
     if (halo_wave) v[EPT - 1] = load_raw(at(src, sb[EPT - 1] + (sx[EPT - 1] & mx) + (sy[EPT - 1] & my)));
   };
@@ -262,19 +284,20 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   // synchronous staging of planes [b0, b1) of a load list into LDS
   auto stage_sync = [&](int first, int b0, int b1) {
     for (int bb = b0; bb < b1; bb += LB) {
-      RW v[LB][EPT];
+      constexpr int LH = LB / SP;  // planes of the batch per thread half
+      RW v[LH][EPT];
       // the records first (clamped into the list: every scalar load is
       // unconditional, so they issue together), then the loads they describe
-      int4 lr[LB];
+      int4 lr[LH];
 #pragma unroll
-      for (int b = 0; b < LB; ++b) lr[b] = rec4(loads, first + min(bb + b, b1 - 1));
+      for (int b = 0; b < LH; ++b) lr[b] = rec4(loads, first + min(bb + SP * b + half, b1 - 1));
 #pragma unroll
-      for (int b = 0; b < LB; ++b)
-        if (bb + b < b1) load_window(v[b], lr[b]);
+      for (int b = 0; b < LH; ++b)
+        if (bb + SP * b + half < b1) load_window(v[b], lr[b]);
 #pragma unroll
-      for (int b = 0; b < LB; ++b) {
-        if (bb + b < b1) {
-          const int4 ld = rec4(loads, first + bb + b);
+      for (int b = 0; b < LH; ++b) {
+        if (bb + SP * b + half < b1) {
+          const int4 ld = lr[b];
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
             if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(wval(v[b], q));
@@ -392,16 +415,17 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     const int4 nxt = has_next ? rec4(orders, o + 1) : make_int4(0, 0, 0, 0);
     const int nl = nxt.y - nxt.x;
     // 1. the next window into registers (every thread loads its own elements)
-    RW stg[MAXP][EPT];
+    constexpr int MH = MAXP / SP;  // planes of the window per thread half
+    RW stg[MH][EPT];
     {
       // the records first (clamped into the list: unconditional scalar loads
       // that issue together), then the loads they describe
-      int4 nrec[MAXP];
+      int4 nrec[MH];
 #pragma unroll
-      for (int b = 0; b < MAXP; ++b) nrec[b] = rec4(loads, nxt.x + max(min(b, nl - 1), 0));
+      for (int b = 0; b < MH; ++b) nrec[b] = rec4(loads, nxt.x + max(min(SP * b + half, nl - 1), 0));
 #pragma unroll
-      for (int b = 0; b < MAXP; ++b)
-        if (b < nl) load_window(stg[b], nrec[b]);
+      for (int b = 0; b < MH; ++b)
+        if (SP * b + half < nl) load_window(stg[b], nrec[b]);
     }
     // 2. the first output rows of the next order
     RW ub[RB][PPT];
@@ -451,9 +475,9 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     // 4. every read of the current window is done: install the next one
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < MAXP; ++b) {
-      if (b < nl) {
-        const int4 ld = rec4(loads, nxt.x + b);
+    for (int b = 0; b < MH; ++b) {
+      if (SP * b + half < nl) {
+        const int4 ld = rec4(loads, nxt.x + SP * b + half);
 #pragma unroll
         for (int q = 0; q < EPT; ++q)
           if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(wval(stg[b], q));
@@ -485,7 +509,7 @@ sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ 
   // the same XCD, one after another, and share its L2
   using C = typename ComputeOf<T>::type;
   const int lb = xcd_tile(blockIdx.x, gridDim.x);
-  if constexpr (kPair<T, TX, TY>) {
+  if constexpr (kPair<T, TX, TY> || kWide<T, TX, TY>) {
     if (pair_fast<T, TX, TY>(a, lb)) {
       sweep_tile<T, TX, TY, CAP, true>(U, decay, (cptr<int>)chunks, (cptr<int>)orders, (cptr<int>)loads,
                                        (cptr<int>)rows, (cptr<C>)rcoef, a, lb);
@@ -565,7 +589,7 @@ sweep_batch_kernel(const BatchEntry* __restrict__ table, const int* __restrict__
   const cptr<int> ldl = (cptr<int>)((gptr<const char>)e.loads[par] + bd);
   const cptr<int> rw = (cptr<int>)((gptr<const char>)e.rows[par] + bd);
   const cptr<C> rc = (cptr<C>)((gptr<const char>)e.rcoef[par] + bd);
-  if constexpr (kPair<T, TX, TY>) {
+  if constexpr (kPair<T, TX, TY> || kWide<T, TX, TY>) {
     if (pair_fast<T, TX, TY>(a, lb)) {
       sweep_tile<T, TX, TY, CAP, true>(u, dec, ch, od, ldl, rw, rc, a, lb);
       return;
