@@ -297,7 +297,8 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
       for (int b = 0; b < LH; ++b) {
         if (bb + SP * b + half < b1) {
-          const int4 ld = lr[b];
+          // read again (a scalar cache hit) rather than kept live across the loads
+          const int4 ld = rec4(loads, first + bb + SP * b + half);
 #pragma unroll
           for (int q = 0; q < EPT; ++q)
             if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(wval(v[b], q));
