@@ -232,7 +232,7 @@ def main(argv=None):
     ap.add_argument("--calibrate-runs", type=int, default=8,
                     help="training instances (indices 0..k-1) for the a-posteriori output scale")
     ap.add_argument("--alphas", default="0.3,0.4,0.5,0.6,0.7,0.8,1.0")
-    ap.add_argument("--loop-rounds", type=int, default=2, help="rounds of training on P_5 + closure states")
+    ap.add_argument("--loop-rounds", type=int, default=4, help="rounds of training on P_5 + closure states")
     ap.add_argument("--loop-runs", type=int, default=400, help="training instances per loop round")
     ap.add_argument("--loop-epochs", type=int, default=3)
     ap.add_argument("--loop-lr", type=float, default=5e-4)
