@@ -76,6 +76,43 @@ def test_c1_line_source_fp64_full_run():
     assert_parity(g, o.u, FP64_TOL, f"C1 P3 100^2 FP64, {s.nsteps} steps:")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_step_and_step_splits(precision):
+    """The degenerate step counts of the composition: a run of one step
+    (S^o_{dt/2} S^e_dt S^o_{dt/2}, three sweeps), advance(0) as a no-op, and one
+    run advanced in uneven pieces (1, 2, 5, 16, 3 steps: graphs of 16/8/4/2/1
+    sweep pairs and their remainders; every piece closes with an odd half-step
+    and the next opens with one, where one advance merges them into a full odd
+    step: equal in exact arithmetic) against one advance over all steps and
+    the oracle."""
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    prob = wl.random_medium(61, 5, 37, t_final=0.8, precision=precision)
+    prob.n = (37, 29)
+    prob.bc = (wl.BC_PERIODIC, wl.BC_EXTRAPOLATION)
+    s = pa.Solver.from_problem(prob)
+    s.bind_torch()
+    assert s.nsteps >= 27
+    init = [m.copy() for m in s.moments()]
+    s.advance(0)
+    assert s.time()[2] == 0
+    assert all(np.array_equal(a, b) for a, b in zip(s.moments(), init))
+    s.advance(1)
+    assert s.time()[2] == 1
+    assert_parity(s.moments(), run_oracle(prob, nsteps=1).u, tol, f"{precision} one step")
+    for k in (2, 5, 16, 3):
+        s.advance(k)
+    pieces = s.moments()
+    assert s.time()[2] == 27
+    s.reset()
+    s.advance(27)
+    whole = s.moments()
+    assert_parity(pieces, whole, tol, f"{precision} pieces against one advance")
+    o = run_oracle(prob, nsteps=27).u
+    assert_parity(whole, o, tol, f"{precision} 27 steps")
+    assert_parity(pieces, o, tol, f"{precision} 27 steps in pieces")
+    s.close()
+
+
 @pytest.mark.parametrize("N", [5, 13, 39])
 def test_tile_variants_are_bitwise_identical(N, monkeypatch):
     """Every compiled tile variant and every split of the moments into m
