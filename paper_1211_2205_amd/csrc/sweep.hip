@@ -304,6 +304,13 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
             if (sv[q]) L[ld.y + db[q] + (ddx[q] & -ld.z) + (ddy[q] & -ld.w)] = S(wval(v[b], q));
         }
       }
+      // Every load of the batch has been consumed.  As at the end of the
+      // order loop, the compiler cannot match the conditional loads with
+      // their conditional stores: without this wait it takes the batch's
+      // registers as possibly still loading at the next batch and waits for
+      // all outstanding loads before each of its loads, one memory round
+      // trip per plane.
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }
   };
 
@@ -398,13 +405,15 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 
   // the padding couplings read this plane of zeros
   for (int e = tid; e < P; e += 256) L[a.zero_off + e] = S(0);
-  // prologue: the first window and the first rows
+  // prologue: the first rows and decay values, then the first window, so
+  // that all of them are in flight together (one memory round trip; the
+  // window's LDS stores wait for the window loads, issued last)
   RW ua[RB][PPT];
   {
     const int4 ord = rec4(orders, chk.x);
-    stage_sync(ord.x, 0, ord.y - ord.x);
     load_rows(ua, ord.z + grp, ord.w);
     prefetch_decay(ord, nc0, nc1);
+    stage_sync(ord.x, 0, ord.y - ord.x);
   }
   __builtin_amdgcn_s_waitcnt(kWaitVm0);  // see the end of the order loop
   __syncthreads();
