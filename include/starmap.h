@@ -333,9 +333,9 @@ int starmap_closure_load(starmap_solver* s, const float* weights, size_t count);
    MI355X): a network kernel writes the closure terms to the closure planes and
    the odd sweep kernel reads them like sources.  Both give the same bits for
    FP64 and FP32 storage (with BF16 storage, 0 rounds the closure terms to
-   bfloat16 on the way through the closure planes).  Batches of closure
-   solvers always use the fused kernel.  STARMAP_ESTATE if the solver is not a
-   closure solver. */
+   bfloat16 on the way through the closure planes).  A batch of closure
+   solvers follows its solvers' setting (they must agree).  STARMAP_ESTATE if
+   the solver is not a closure solver. */
 int starmap_closure_set_fused(starmap_solver* s, int32_t enable);
 
 /* Training samples from the current state of a solver of order N >= 6
@@ -478,8 +478,11 @@ int starmap_reset(starmap_solver* s);
    data, and outlive the batch; their results are read with the per-solver
    calls.  A batch holds either no closure solvers or only closure solvers
    (STARMAP_CLOSURE_LEARNED, network loaded, one network for all): then every
-   odd sweep is one launch of the fused closure kernel (see
-   starmap_closure_set_fused) over all running instances.  While in a batch, a solver's tile variant is the batch's: do not
+   odd sweep is, with the solvers' default (starmap_closure_set_fused 0), one
+   launch of the network over all running instances followed by one batched
+   odd sweep, or with fused solvers one launch of the fused closure kernel
+   over all running instances; starmap_batch_run returns STARMAP_EINVAL if the
+   solvers' settings differ.  While in a batch, a solver's tile variant is the batch's: do not
    call starmap_set_variant on it. */
 typedef struct starmap_batch starmap_batch;
 

@@ -1804,6 +1804,10 @@ struct starmap_batch {
   // int cfirst[count + 1] (evaluation blocks of the closure sweep per
   // instance, in the group's order)
   bool closure = false;
+  // closure batches: the solvers' setting (starmap_closure_set_fused), read at
+  // every run: one fused kernel per odd sweep, or the network then a batched
+  // odd sweep
+  bool closure_fused = false;
   void* ctab = nullptr;
   std::vector<int> cfirst;
   // captured run
@@ -1912,6 +1916,12 @@ int items_of(const starmap_solver* s) {
 int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau) {
   const int count = int(b->inst.size());
   const int ng = int(b->groups.size());
+  if (b->closure) {
+    b->closure_fused = b->inst[0]->closure_fused;
+    for (const auto* s : b->inst)
+      if (s->closure_fused != b->closure_fused)
+        return fail(STARMAP_EINVAL, "the closure solvers of a batch must agree on starmap_closure_set_fused");
+  }
   b->plans.clear();
   if (b->merged && ng > 1) {
     BatchPlan pl;
@@ -1980,7 +1990,7 @@ int batch_table(starmap_batch* b, const std::vector<int>& sweeps, bool zero_tau)
       e.nchunks = int(s->prog[0].chunks.size());
       e.nsweeps = sweeps[ord[r]];
       e.strip = s->tile_strip;
-      e.even_b_delta = s->closure ? int64_t(s->off_prog_b) - int64_t(s->off_prog[0]) : 0;
+      e.even_b_delta = (s->closure && b->closure_fused) ? int64_t(s->off_prog_b) - int64_t(s->off_prog[0]) : 0;
       tab.push_back(e);
       g.nsweeps[r] = sweeps[ord[r]];
       g.first[r] = int(total);
@@ -2037,7 +2047,8 @@ int batch_launch(starmap_batch* b, int j0, int j1, int only = -1) {
       reinterpret_cast<const int*>(static_cast<char*>(b->dtab) + align256(b->inst.size() * sizeof(BatchEntry)));
   for (int j = j0; j < j1; ++j) {
     if (b->closure && (j & 1) == 0) {
-      // odd sweep of closure solvers: the network and the odd update in one kernel
+      // odd sweep of closure solvers: the network and the odd update in one
+      // kernel, or the network alone here and the odd sweep below
       const BatchPlan& g = b->plans[0];
       int na = int(g.nsweeps.size());
       while (na > 0 && g.nsweeps[na - 1] <= j) --na;
@@ -2046,9 +2057,12 @@ int batch_launch(starmap_batch* b, int j0, int j1, int only = -1) {
       const int* cf = reinterpret_cast<const int*>(static_cast<char*>(b->ctab) +
                                                    align256(b->inst.size() * sizeof(ClosureInst)));
       const starmap_solver* s0 = b->inst[g.order[0]];
-      HIP_TRY(launch_closure_batch(b->storage, ct, cf, na, b->cfirst[na], j,
-                                   reinterpret_cast<const ClosureNet*>(dptr(s0, s0->off_net)), b->stream));
-      continue;
+      const ClosureNet* net = reinterpret_cast<const ClosureNet*>(dptr(s0, s0->off_net));
+      if (b->closure_fused) {
+        HIP_TRY(launch_closure_batch(b->storage, ct, cf, na, b->cfirst[na], j, net, b->stream));
+        continue;
+      }
+      HIP_TRY(launch_closure_batch_net(b->storage, ct, cf, na, b->cfirst[na], net, b->stream));
     }
     for (int gi = 0; gi < int(b->plans.size()); ++gi) {
       if (only >= 0 && gi != only) continue;
@@ -2286,15 +2300,16 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
   for (const auto& g : b->plans) {
     if (!g.nsweeps.empty()) jmax = std::max(jmax, g.nsweeps[0]);
     for (int j = 0; !g.nsweeps.empty() && j < g.nsweeps[0]; ++j)
-      if (!(b->closure && (j & 1) == 0)) ++launches;
+      if (!(b->closure && b->closure_fused && (j & 1) == 0)) ++launches;
   }
+  // closure batches: one network launch (fused: network and odd sweep) per odd sweep
   if (b->closure && !b->plans[0].nsweeps.empty()) launches += (b->plans[0].nsweeps[0] + 1) / 2;
   HIP_TRY(hipEventRecord(b->ev[0], b->stream));
   if (jmax > 0) {
     if (use_graph) {
       // the graph depends on every group's tile (kernel, LDS, programs) and
       // on the launch plans
-      std::vector<int> key{b->merged ? 1 : 0};
+      std::vector<int> key{b->merged ? 1 : 0, b->closure_fused ? 1 : 0};
       for (const auto& g : b->groups) key.insert(key.end(), {g.variant, g.width, g.slots});
       for (const auto& g : b->plans) {
         key.insert(key.end(), {g.variant, g.slots, int(g.nsweeps.size())});
@@ -2333,8 +2348,8 @@ int starmap_batch_run(starmap_batch* b, int32_t use_graph) {
     const BatchPlan& g = b->plans[0];
     for (size_t r = 0; r < g.order.size(); ++r) {
       starmap_solver* s = b->inst[g.order[r]];
-      // (nsweeps + 1) / 2 odd sweeps each moved the order-5 moments once
-      s->c5_flip = ((g.nsweeps[r] + 1) / 2) & 1;
+      // fused: (nsweeps + 1) / 2 odd sweeps each moved the order-5 moments once
+      s->c5_flip = b->closure_fused ? ((g.nsweeps[r] + 1) / 2) & 1 : 0;
       rc = closure_settle(s);
       if (rc) return rc;
       HIP_TRY(hipStreamSynchronize(s->stream));
@@ -2400,8 +2415,8 @@ int starmap_batch_autotune(starmap_batch* b, int32_t sweeps) {
         int rc = group_prepare(b, g, v, w);
         if (rc) return rc;
         // three sweeps: odd, even, odd.  A closure batch times the first pair
-        // (odd sweep 0 copies the order-5 moments into the closure planes,
-        // even sweep 1 reads them there)
+        // (odd sweep 0 evaluates the network; fused, it also moves the order-5
+        // moments into the closure planes, where even sweep 1 reads them)
         const int j0 = b->closure ? 0 : 1;
         rc = batch_table(b, std::vector<int>(count, 3), true);
         if (!rc) rc = batch_launch(b, j0, j0 + 2, gi);

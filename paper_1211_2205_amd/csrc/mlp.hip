@@ -371,11 +371,13 @@ __device__ __forceinline__ C closure_odd_update(const T* __restrict__ U, const C
 // out5 (out of place, so every workgroup's stencils see the state of the
 // start of the sweep), orders 1 and 3 in place (nothing else reads them).
 //
-// BATCH = true (with FUSED): odd sweep number j of a batched run of closure
-// solvers sharing one network; instance i (of the n_active still running,
-// sorted by their sweep counts) owns the evaluation blocks
-// [bfirst[i], bfirst[i + 1]) and brings its own state, geometry and odd rows
-// (insts[i]); the arguments U .. odd are unused.
+// BATCH = true: odd sweep number j of a batched run of closure solvers
+// sharing one network; instance i (of the n_active still running, sorted by
+// their sweep counts) owns the evaluation blocks [bfirst[i], bfirst[i + 1])
+// and brings its own state, geometry and odd rows (insts[i]); the arguments
+// U .. odd are unused.  With FUSED the kernel performs the odd sweeps as
+// above; without, it writes every instance's closure planes, and a batched
+// odd sweep follows.
 template <typename T, bool FUSED, bool BATCH>
 __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U0, const T* __restrict__ in5_0,
                                                             T* __restrict__ out5_0,
@@ -385,7 +387,6 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
                                                             const ClosureInst* __restrict__ insts,
                                                             const int* __restrict__ bfirst, const int n_active,
                                                             const int jsweep) {
-  static_assert(FUSED || !BATCH, "batched runs use the fused sweep");
   using C = typename ComputeOf<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* Xa = reinterpret_cast<uint16_t*>(smem);  // [64][LDW] inputs, then layer-2 activations
@@ -399,16 +400,18 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
   const int fk = 8 * (lane >> 4);
 
   // the output geometry, indexed per lane below, from LDS (indexing the
-  // kernel argument per lane would turn every access into a dependent load)
-  const ClosureGeo& Gk = G0;
-  if (!FUSED && tid < 5 * 8) {
-    const ClosureGeo& G = Gk;
-    const int f = tid >> 3, o = tid & 7;
-    int v = 0;
-    if (o < CLOSURE_OUT)
-      v = f == 0 ? G.q[o] : f == 1 ? G.out_nx[o] : f == 2 ? G.out_ny[o] : f == 3 ? G.out_nodex[o] : G.out_nodey[o];
-    otab[tid] = v;
-  }
+  // kernel argument per lane would turn every access into a dependent load);
+  // batched: each block's instance's, written at the start of the block
+  auto fill_otab = [&](const ClosureGeo& G) {
+    if (tid < 5 * 8) {
+      const int f = tid >> 3, o = tid & 7;
+      int v = 0;
+      if (o < CLOSURE_OUT)
+        v = f == 0 ? G.q[o] : f == 1 ? G.out_nx[o] : f == 2 ? G.out_ny[o] : f == 3 ? G.out_nodex[o] : G.out_nodey[o];
+      otab[tid] = v;
+    }
+  };
+  if constexpr (!FUSED && !BATCH) fill_otab(G0);
 
   // this wave's weight fragments: rows 32 w + 16 mi + (lane % 16), k = 32 ks + fk
   const uint4* wv = reinterpret_cast<const uint4*>(net->w);  // rows of CLOSURE_IN / 8 uint4
@@ -449,7 +452,7 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
     // the order-5 moments move between the state planes and the closure
     // planes at every odd sweep: odd sweep j of a batched run reads them
     // where j / 2 earlier odd sweeps left them
-    const bool flip = BATCH && ((jsweep >> 1) & 1);
+    const bool flip = BATCH && FUSED && ((jsweep >> 1) & 1);
     const T* const in5 = BATCH ? static_cast<const T*>(flip ? insts[inst].b5 : insts[inst].a5) : in5_0;
     T* const out5 = BATCH ? static_cast<T*>(flip ? insts[inst].a5 : insts[inst].b5) : out5_0;
     const C tau = BATCH ? C((jsweep == 0 || jsweep == insts[inst].nsweeps - 1) ? insts[inst].tau_half
@@ -505,8 +508,9 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
 #pragma unroll
       for (int q = 0; q < 9; ++q) v0[q] = to_c(up[rowy[cy][q / 3] + colx[cx][q % 3]]);
     }
-    __syncthreads();  // the previous block's reads of Xa, nu_s and part are done
+    __syncthreads();  // the previous block's reads of Xa, nu_s, part and otab are done
     part[w * CB + lane] = ss;
+    if constexpr (!FUSED && BATCH) fill_otab(G);
     __syncthreads();
     const C nu = sqrt(((part[lane] + part[CB + lane]) + part[2 * CB + lane]) + part[3 * CB + lane]) + C(CLOSURE_EPS);
     const C rnu = C(1) / nu;
@@ -784,6 +788,26 @@ hipError_t launch_closure_sweep(int storage, void* U, const void* in5, void* out
     case STORE_BF16:
       return launch_infer_t<bf16, true, false>(U, in5, out5, decay, G, net, odd, nullptr, nullptr, 0, 0, blocks,
                                                stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_closure_batch_net(int storage, const ClosureInst* insts, const int* bfirst, int n_active, int blocks,
+                                    const ClosureNet* net, hipStream_t stream) {
+  if (n_active < 1 || blocks < 1) return hipErrorInvalidValue;
+  const int grid = std::min(blocks, 3 * device_cus());
+  const ClosureGeo G{};
+  const ClosureOdd odd{};
+  switch (storage) {
+    case STORE_FP64:
+      return launch_infer_t<double, false, true>(nullptr, nullptr, nullptr, nullptr, G, net, odd, insts, bfirst,
+                                                 n_active, 0, grid, stream);
+    case STORE_FP32:
+      return launch_infer_t<float, false, true>(nullptr, nullptr, nullptr, nullptr, G, net, odd, insts, bfirst,
+                                                n_active, 0, grid, stream);
+    case STORE_BF16:
+      return launch_infer_t<bf16, false, true>(nullptr, nullptr, nullptr, nullptr, G, net, odd, insts, bfirst,
+                                               n_active, 0, grid, stream);
   }
   return hipErrorInvalidValue;
 }

@@ -134,6 +134,11 @@ hipError_t launch_closure_sweep(int storage, void* U, const void* in5, void* out
 // bfirst[i]; one network for all.
 hipError_t launch_closure_batch(int storage, const ClosureInst* insts, const int* bfirst, int n_active, int blocks,
                                 int j, const ClosureNet* net, hipStream_t stream);
+// The network alone over a batch of closure solvers (BATCH mode without the
+// fused sweep): every running instance's closure planes, which its odd sweep
+// then reads as sources.
+hipError_t launch_closure_batch_net(int storage, const ClosureInst* insts, const int* bfirst, int n_active, int blocks,
+                                    const ClosureNet* net, hipStream_t stream);
 size_t closure_infer_lds_bytes();
 
 }  // namespace starmap

@@ -288,10 +288,13 @@ def test_fused_closure_bf16_storage_close_to_separate():
     assert rel_l2(outs[0], outs[1]) < 2e-2
 
 
-def test_batched_closure_solvers_equal_single_runs():
+@pytest.mark.parametrize("fused", [False, True])
+def test_batched_closure_solvers_equal_single_runs(fused):
     """A batch of closure solvers (one network; ragged grids and every boundary
-    mix; uneven step counts): each instance ends bitwise equal to its own
-    single-solver run, with graphs and without, after the batch autotuner."""
+    mix; uneven step counts), with the network and a batched odd sweep per odd
+    sweep or the fused kernel: each instance ends bitwise equal to its own
+    single-solver run (two kernels), with graphs and without, after the batch
+    autotuner."""
     p = mlp.flatten(_params(13, out_scale=0.2))
     cases = [((24, 20), (wl.BC_EXTRAPOLATION, wl.BC_EXTRAPOLATION), 41),
              ((33, 16), (wl.BC_PERIODIC, wl.BC_EXTRAPOLATION), 42),
@@ -311,6 +314,7 @@ def test_batched_closure_solvers_equal_single_runs():
             for prob in probs:
                 s = pa.Solver.from_problem(prob, precision=precision, closure="learned")
                 s.load_closure(p)
+                s.set_closure_fused(fused)
                 solvers.append(s)
             b = pa.Batch(solvers)
             b.autotune(1)
@@ -321,7 +325,8 @@ def test_batched_closure_solvers_equal_single_runs():
             b.close()
             for s in solvers:
                 s.close()
-        print(f"batched closure {precision}: {len(probs)} instances identical to single runs", flush=True)
+        print(f"batched closure {precision} (fused {fused}): {len(probs)} instances identical to single runs",
+              flush=True)
 
 
 def test_batched_closure_rules():
@@ -340,3 +345,10 @@ def test_batched_closure_rules():
     d = pa.Solver.from_problem(prob, closure="learned")
     with pytest.raises(pa.StarmapError):
         pa.Batch([d])          # no network loaded
+    e = pa.Solver.from_problem(prob, closure="learned")
+    e.load_closure(p)
+    e.set_closure_fused(True)
+    b = pa.Batch([a, e])
+    with pytest.raises(pa.StarmapError):
+        b.run()                # fused and two-kernel solvers together
+    b.close()
