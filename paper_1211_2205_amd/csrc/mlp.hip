@@ -449,9 +449,10 @@ __global__ void __launch_bounds__(256, 3) closure_infer_kernel(T* __restrict__ U
     const ClosureOdd& odd = BATCH ? insts[inst].odd : odd0;
     T* const U = BATCH ? static_cast<T*>(insts[inst].u) : U0;
     const C* const decay = BATCH ? static_cast<const C*>(insts[inst].decay) : decay0;
-    // the order-5 moments move between the state planes and the closure
-    // planes at every odd sweep: odd sweep j of a batched run reads them
-    // where j / 2 earlier odd sweeps left them
+    // fused: the order-5 moments move between the state planes and the
+    // closure planes at every odd sweep, and odd sweep j of a batched run
+    // reads them where j / 2 earlier odd sweeps left them (the network alone
+    // reads them in the state planes)
     const bool flip = BATCH && FUSED && ((jsweep >> 1) & 1);
     const T* const in5 = BATCH ? static_cast<const T*>(flip ? insts[inst].b5 : insts[inst].a5) : in5_0;
     T* const out5 = BATCH ? static_cast<T*>(flip ? insts[inst].a5 : insts[inst].b5) : out5_0;
