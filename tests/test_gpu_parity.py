@@ -113,6 +113,22 @@ def test_single_step_and_step_splits(precision):
     s.close()
 
 
+def test_maximum_order_p99():
+    """The largest moment order the library accepts, N = 99 (5050 moments, 17
+    m ranges of the default width), on a ragged 20 x 13 grid with an
+    extrapolation and a periodic axis: the whole run (5 steps) against the
+    oracle, FP64."""
+    prob = wl.random_medium(71, 99, 20, t_final=0.25, precision="fp64")
+    prob.n = (20, 13)
+    prob.bc = (wl.BC_EXTRAPOLATION, wl.BC_PERIODIC)
+    s = pa.Solver.from_problem(prob)
+    s.bind_torch()
+    assert s.nsteps == 5
+    s.run()
+    assert_parity(s.moments(), run_oracle(prob).u, FP64_TOL, "P_99 20x13, 5 steps")
+    s.close()
+
+
 @pytest.mark.parametrize("N", [5, 13, 39])
 def test_tile_variants_are_bitwise_identical(N, monkeypatch):
     """Every compiled tile variant and every split of the moments into m
