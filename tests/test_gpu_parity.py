@@ -46,6 +46,8 @@ SMALL = [
     (9, (65, 66), ("periodic", "periodic"), False, True),
     (15, (20, 33), ("extrapolation", "extrapolation"), False, False),
     (39, (17, 12), ("extrapolation", "periodic"), False, True),
+    (2, (2, 2), ("periodic", "periodic"), True, True),
+    (2, (5, 2), ("extrapolation", "periodic"), False, True),
 ]
 
 
