@@ -508,8 +508,16 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   }
 }
 
+// Waves per SIMD the compiler is asked to fit (1: no bound).  The FP32
+// 32 x 8 tile with eight planes in registers is held to seven: it needs two
+// registers more than seven waves allow, and at m-range width 6 its LDS
+// admits seven workgroups per CU.  (The batched kernel, which reads its
+// instance table as well, would spill at that bound and keeps none.)
 template <typename T, int TX, int TY, int CAP>
-__global__ void __launch_bounds__(256)
+constexpr int kMinWaves = (sizeof(T) == 4 && TX == 32 && TY == 8 && CAP == 8) ? 7 : 1;
+
+template <typename T, int TX, int TY, int CAP>
+__global__ void __launch_bounds__(256, (kMinWaves<T, TX, TY, CAP>))
 sweep_kernel(T* __restrict__ U, const typename ComputeOf<T>::type* __restrict__ decay,
              const int4* __restrict__ chunks, const int4* __restrict__ orders,
              const int4* __restrict__ loads, const int* __restrict__ rows,
