@@ -481,8 +481,8 @@ int starmap_reset(starmap_solver* s);
    odd sweep is, with the solvers' default (starmap_closure_set_fused 0), one
    launch of the network over all running instances followed by one batched
    odd sweep, or with fused solvers one launch of the fused closure kernel
-   over all running instances; starmap_batch_run returns STARMAP_EINVAL if the
-   solvers' settings differ.  While in a batch, a solver's tile variant is the batch's: do not
+   over all running instances; starmap_batch_run and starmap_batch_autotune
+   return STARMAP_EINVAL if the solvers' settings differ.  While in a batch, a solver's tile variant is the batch's: do not
    call starmap_set_variant on it. */
 typedef struct starmap_batch starmap_batch;
 
