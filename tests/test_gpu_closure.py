@@ -300,7 +300,9 @@ def test_batched_closure_solvers_equal_single_runs(fused):
              ((33, 16), (wl.BC_PERIODIC, wl.BC_EXTRAPOLATION), 42),
              ((20, 41), (wl.BC_EXTRAPOLATION, wl.BC_PERIODIC), 43),
              ((48, 48), (wl.BC_PERIODIC, wl.BC_PERIODIC), 44)]
-    for precision in ("fp64", "fp32"):
+    # BF16 only with two kernels: the fused kernel keeps the closure terms in
+    # FP32, the two-kernel path rounds them through the BF16 closure planes
+    for precision in ("fp64", "fp32") + (() if fused else ("bf16",)):
         probs = [_state_problem(5, n, bc, seed, precision=precision) for n, bc, seed in cases]
         singles = []
         for prob in probs:
