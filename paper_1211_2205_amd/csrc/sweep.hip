@@ -95,13 +95,15 @@ constexpr int kWaitVm0 = 0x0F70;
 // would move half the bytes per instruction.
 template <typename T, int TX, int TY>
 constexpr bool kPair = sizeof(T) == 2 && TX * TY == 512;
-// FP64 and FP32 on tiles of 256 points whose halo fits 128 threads: the
-// window is staged by two halves of the workgroup, each half taking every
-// other plane, each thread two x-adjacent points of it with one 16-byte
-// (8-byte) load where the pair lies inside the grid: half as many vector
-// memory instructions per staged plane as one point per thread.
+// FP64 and FP32 on tiles of 256 points, BF16 on tiles of 512, whose halo
+// fits 128 threads: the window is staged by two halves of the workgroup, each
+// half taking every other plane, each thread two (BF16: four) x-adjacent
+// points of it with one 16-byte (FP32, BF16: 8-byte) load where they lie
+// inside the grid: fewer vector memory instructions per staged plane than
+// one point (BF16: one pair) per thread.
 template <typename T, int TX, int TY>
-constexpr bool kWide = sizeof(T) >= 4 && TX * TY == 256 && TX + TY <= 128 && TX % 2 == 0;
+constexpr bool kWide = (sizeof(T) >= 4 ? TX * TY == 256 && TX % 2 == 0 : TX * TY == 512 && TX % 4 == 0) &&
+                       TX + TY <= 128;
 
 // Whether work item lb lies on a tile whose pairs all lie inside the grid
 // along x (FAST = true below); uniform over the workgroup.
@@ -143,7 +145,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   constexpr bool PAIR = kPair<T, TX, TY>;
   constexpr bool WIDE = kWide<T, TX, TY>;
   static_assert(PAIR || WIDE || !FAST, "the pair paths are for BF16 tiles of 512 points and wide staging");
-  constexpr int SE = WIDE ? 2 : PPT;    // staged interior points per thread and plane
+  constexpr int SE = WIDE ? NP / 128 : PPT;  // staged interior points per thread and plane
   constexpr int EPT = SE + 1;           // staged points per thread and plane: interior + halo
   constexpr int SP = WIDE ? 2 : 1;      // thread halves that take turns in the planes of a window
   static_assert(MAXP % SP == 0 && LB % SP == 0, "planes split evenly over the thread halves");
@@ -184,7 +186,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   bool sv[EPT];
 #pragma unroll
   for (int p = 0; p < SE; ++p) {
-    const int e = (PAIR || WIDE) ? 2 * st + p : tid + p * 256;
+    const int e = WIDE ? SE * st + p : PAIR ? 2 * st + p : tid + p * 256;
     const int tx = e % TX, ty = e / TX;
     const int xn = map_axis(x0 + tx, a.nx, a.px, 0), xc = map_axis(x0 + tx, a.nx, a.px, 1);
     const int yn = map_axis(y0 + ty, a.ny, a.py, 0), yc = map_axis(y0 + ty, a.ny, a.py, 1);
@@ -253,27 +255,33 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   auto load_window = [&](RW (&v)[EPT], const int4 ld) {
     const T* src = plane_at(U, ld.x, a.ps);
     const uint32_t mx = 0u - uint32_t(ld.z), my = 0u - uint32_t(ld.w);
-    if constexpr (PAIR && pfast) {
+    if constexpr (WIDE && pfast) {
+      // the points are contiguous and aligned to their total size (x a
+      // multiple of SE, pitch and plane stride multiples of 64 elements)
+      if constexpr (sizeof(T) == 2) {  // four BF16 values as two raw words
+        const uint2 w = *reinterpret_cast<const uint2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+        v[0] = w.x;
+        v[1] = w.y;
+      } else {
+        using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
+        const T2 w = *reinterpret_cast<const T2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+        v[0] = w.x;
+        v[1] = w.y;
+      }
+    } else if constexpr (PAIR && pfast) {
       v[0] = *reinterpret_cast<const uint32_t*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
-    } else if constexpr (WIDE && pfast) {
-      // the pair is contiguous and aligned to its size (even x, pitch and
-      // plane stride multiples of 64 elements)
-      using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
-      const T2 w = *reinterpret_cast<const T2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
-      v[0] = w.x;
-      v[1] = w.y;
     } else {
 #pragma unroll
       for (int q = 0; q < SE; ++q) v[q] = load_raw(at(src, sb[q] + (sx[q] & mx) + (sy[q] & my)));
     }
     if (halo_wave) v[EPT - 1] = load_raw(at(src, sb[EPT - 1] + (sx[EPT - 1] & mx) + (sy[EPT - 1] & my)));
   };
-  // value of staged point q of a window's registers
+  // value of staged point q of a window's registers (BF16 interior points
+  // on the fast tiles: packed two to a word, the lower x in the low half)
   auto wval = [&](const RW (&v)[EPT], int q) -> C {
     if constexpr (sizeof(T) == 2) {
-      if constexpr (PAIR && pfast) {
-        if (q == 0) return __uint_as_float(v[0] << 16);
-        if (q == 1) return __uint_as_float(v[0] & 0xFFFF0000u);
+      if constexpr ((PAIR || WIDE) && pfast) {
+        if (q < SE) return __uint_as_float((q & 1) ? (v[q >> 1] & 0xFFFF0000u) : (v[q >> 1] << 16));
       }
       return __uint_as_float(v[q] << 16);
     } else {
