@@ -95,14 +95,16 @@ constexpr int kWaitVm0 = 0x0F70;
 // would move half the bytes per instruction.
 template <typename T, int TX, int TY>
 constexpr bool kPair = sizeof(T) == 2 && TX * TY == 512;
-// FP64 and FP32 on tiles of 256 points, BF16 on tiles of 512, whose halo
-// fits 128 threads: the window is staged by two halves of the workgroup, each
-// half taking every other plane, each thread two (BF16: four) x-adjacent
-// points of it with one 16-byte (FP32, BF16: 8-byte) load where they lie
-// inside the grid: fewer vector memory instructions per staged plane than
-// one point (BF16: one pair) per thread.
+// FP64 and FP32 on tiles of 256 points, FP32 and BF16 on tiles of 512,
+// whose halo fits 128 threads: the window is staged by two halves of the
+// workgroup, each half taking every other plane, each thread two (512-point
+// tiles: four) x-adjacent points of it with one load of 16 bytes (FP32 on
+// 256 points, BF16: 8) where they lie inside the grid: fewer vector memory
+// instructions per staged plane than one point (BF16: one pair) per thread.
 template <typename T, int TX, int TY>
-constexpr bool kWide = (sizeof(T) >= 4 ? TX * TY == 256 && TX % 2 == 0 : TX * TY == 512 && TX % 4 == 0) &&
+constexpr bool kWide = (sizeof(T) == 8 ? TX * TY == 256 && TX % 2 == 0
+                        : sizeof(T) == 4 ? (TX * TY == 256 && TX % 2 == 0) || (TX * TY == 512 && TX % 4 == 0)
+                                         : TX * TY == 512 && TX % 4 == 0) &&
                        TX + TY <= 128;
 
 // Whether work item lb lies on a tile whose pairs all lie inside the grid
@@ -262,6 +264,12 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         const uint2 w = *reinterpret_cast<const uint2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
         v[0] = w.x;
         v[1] = w.y;
+      } else if constexpr (SE == 4) {  // four FP32 values
+        const float4 w = *reinterpret_cast<const float4*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+        v[0] = w.x;
+        v[1] = w.y;
+        v[2] = w.z;
+        v[3] = w.w;
       } else {
         using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
         const T2 w = *reinterpret_cast<const T2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
