@@ -79,7 +79,18 @@ __device__ __forceinline__ uint32_t load_pair_stream(const bf16* p) {
 __device__ __forceinline__ void store_pair_stream(bf16* p, bf16 lo, bf16 hi) {
   __builtin_nontemporal_store(uint32_t(lo.bits) | (uint32_t(hi.bits) << 16), reinterpret_cast<uint32_t*>(p));
 }
+// Two x-adjacent FP32 values as one 8-byte access (8-byte aligned).
+typedef float float2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2v load_pair2_stream(const float* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const float2v*>(p));
+}
+__device__ __forceinline__ void store_pair_stream(float* p, float lo, float hi) {
+  const float2v v = {lo, hi};
+  __builtin_nontemporal_store(v, reinterpret_cast<float2v*>(p));
+}
 // (never called for the other storage types)
+template <typename T>
+__device__ __forceinline__ float2v load_pair2_stream(const T*) { return float2v{0.f, 0.f}; }
 template <typename T>
 __device__ __forceinline__ uint32_t load_pair_stream(const T*) { return 0; }
 template <typename T>
@@ -89,12 +100,16 @@ __device__ __forceinline__ void store_pair_stream(T*, T, T) {}
 // (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
 
-// BF16 on tiles of 512 points: each thread owns two x-adjacent points, and
-// on tiles away from the right edge of the grid (where no staging index is
-// clamped or wrapped) the pair moves as one 32-bit access: 2-byte accesses
-// would move half the bytes per instruction.
+// BF16 on tiles of 512 points, and FP32 on 32 x 16 tiles: each thread owns
+// two x-adjacent points, and on tiles away from the right edge of the grid
+// (where no staging index is clamped or wrapped) the pair moves as one 32-bit
+// (FP32: 64-bit) access: single accesses would move half the bytes per
+// instruction.  FP32 only on 32-wide tiles: there the 32 lanes of a half-wave
+// read two whole rows of the LDS window (row pitch 33 words) with their
+// stride-2 stencil reads, each bank once; on 64- and 128-wide tiles the same
+// reads hit every other bank twice and the sweep got slower.
 template <typename T, int TX, int TY>
-constexpr bool kPair = sizeof(T) == 2 && TX * TY == 512;
+constexpr bool kPair = TX * TY == 512 && (sizeof(T) == 2 || (sizeof(T) == 4 && TX == 32));
 // FP64 and FP32 on tiles of 256 points, FP32 and BF16 on tiles of 512,
 // whose halo fits 128 threads: the window is staged by two halves of the
 // workgroup, each half taking every other plane, each thread two (512-point
@@ -277,7 +292,13 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
         v[1] = w.y;
       }
     } else if constexpr (PAIR && pfast) {
-      v[0] = *reinterpret_cast<const uint32_t*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+      if constexpr (sizeof(T) == 2) {
+        v[0] = *reinterpret_cast<const uint32_t*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+      } else {
+        const float2 w = *reinterpret_cast<const float2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
+        v[0] = w.x;
+        v[1] = w.y;
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < SE; ++q) v[q] = load_raw(at(src, sb[q] + (sx[q] & mx) + (sy[q] & my)));
@@ -331,7 +352,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   };
 
   // current values of the output rows r0, r0 + NG, ... (RB of them, < r1),
-  // raw (a pair: one word in uv[i][0])
+  // raw (a BF16 pair: one word in uv[i][0])
   auto load_rows = [&](RW (&uv)[RB][PPT], int r0, int r1) {
     // plane and grid slot of every row first (row indices clamped into the
     // table: unconditional scalar loads that issue together), then the loads
@@ -349,10 +370,15 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
       if (r < r1) {
         const T* up = plane_at(U, rk[i], a.ps);
         const bool s1 = rs[i] != 0;
-        if constexpr (PAIR && pfast) {  // both points of the pair lie inside the output grid along x
+        if constexpr (PAIR && pfast && sizeof(T) == 2) {  // both points of the pair lie inside the output grid along x
           uint32_t w = 0;
           if (s1 ? val1[0] : val0[0]) w = load_pair_stream(at(up, goff[0] * TS));
           uv[i][0] = w;
+        } else if constexpr (PAIR && pfast) {
+          float2v w = {0.f, 0.f};
+          if (s1 ? val1[0] : val0[0]) w = load_pair2_stream(at(up, goff[0] * TS));
+          uv[i][0] = w.x;
+          uv[i][1] = w.y;
         } else {
 #pragma unroll
           for (int p = 0; p < PPT; ++p)
@@ -520,7 +546,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int p = 0; p < (PAIR && pfast ? 1 : PPT); ++p) ua[i][p] = ub[i][p];
+      for (int p = 0; p < (PAIR && pfast && sizeof(T) == 2 ? 1 : PPT); ++p) ua[i][p] = ub[i][p];
   }
 }
 
