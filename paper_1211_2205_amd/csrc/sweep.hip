@@ -100,16 +100,12 @@ __device__ __forceinline__ void store_pair_stream(T*, T, T) {}
 // (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
 
-// BF16 on tiles of 512 points, and FP32 on 32 x 16 tiles: each thread owns
-// two x-adjacent points, and on tiles away from the right edge of the grid
-// (where no staging index is clamped or wrapped) the pair moves as one 32-bit
-// (FP32: 64-bit) access: single accesses would move half the bytes per
-// instruction.  FP32 only on 32-wide tiles: there the 32 lanes of a half-wave
-// read two whole rows of the LDS window (row pitch 33 words) with their
-// stride-2 stencil reads, each bank once; on 64- and 128-wide tiles the same
-// reads hit every other bank twice and the sweep got slower.
+// BF16 and FP32 on tiles of 512 points: each thread owns two x-adjacent
+// output points, and on tiles away from the right edge of the grid (where no
+// staging index is clamped or wrapped) the pair moves as one 32-bit (FP32:
+// 64-bit) access: single accesses would move half the bytes per instruction.
 template <typename T, int TX, int TY>
-constexpr bool kPair = TX * TY == 512 && (sizeof(T) == 2 || (sizeof(T) == 4 && TX == 32));
+constexpr bool kPair = TX * TY == 512 && (sizeof(T) == 2 || sizeof(T) == 4);
 // FP64 and FP32 on tiles of 256 points, FP32 and BF16 on tiles of 512,
 // whose halo fits 128 threads: the window is staged by two halves of the
 // workgroup, each half taking every other plane, each thread two (512-point
@@ -254,8 +250,21 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     const int vx1 = a.parity ? nxc : nxn, vy1 = a.parity ? nyn : nyn;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      const int e = PAIR ? 2 * tid + p : tid + p * 256;
-      const int tx = e % TX, ty = e / TX;
+      int tx, ty;
+      if constexpr (PAIR) {
+        // each half-wave owns a 32 x 2 block of the tile, 16 lanes per row:
+        // its stride-2 stencil reads of the LDS window (row pitch TX + 1,
+        // an odd number of words) then meet each of the 32 banks once
+        static_assert(TX % 32 == 0 && TY % 2 == 0, "pair tiles are made of 32 x 2 blocks");
+        constexpr int CB = TX / 32;  // blocks per tile row
+        const int u = tid >> 5;
+        tx = (u % CB) * 32 + 2 * (tid & 15) + p;
+        ty = 2 * (u / CB) + ((tid >> 4) & 1);
+      } else {
+        const int e = tid + p * 256;
+        tx = e % TX;
+        ty = e / TX;
+      }
       const int X = x0 + tx, Y = y0 + ty;
       pos[p] = ty * LW + tx;
       goff[p] = uint32_t(Y * a.pitch + X);
@@ -294,7 +303,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
     } else if constexpr (PAIR && pfast) {
       if constexpr (sizeof(T) == 2) {
         v[0] = *reinterpret_cast<const uint32_t*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
-      } else {
+      } else {  // FP32 pair tiles too wide for the wide staging (128 x 4)
         const float2 w = *reinterpret_cast<const float2*>(at(src, sb[0] + (sx[0] & mx) + (sy[0] & my)));
         v[0] = w.x;
         v[1] = w.y;
