@@ -157,7 +157,7 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
   constexpr int LB = sizeof(T) >= 8 ? 8 : 16;  // planes per batch of the synchronous staging
   constexpr bool PAIR = kPair<T, TX, TY>;
   constexpr bool WIDE = kWide<T, TX, TY>;
-  static_assert(PAIR || WIDE || !FAST, "the pair paths are for BF16 tiles of 512 points and wide staging");
+  static_assert(PAIR || WIDE || !FAST, "the fast paths are for pair tiles (512 points) and wide staging");
   constexpr int SE = WIDE ? NP / 128 : PPT;  // staged interior points per thread and plane
   constexpr int EPT = SE + 1;           // staged points per thread and plane: interior + halo
   constexpr int SP = WIDE ? 2 : 1;      // thread halves that take turns in the planes of a window
@@ -184,8 +184,9 @@ __device__ __forceinline__ void sweep_tile(T* __restrict__ U, const typename Com
 
   // Staging of one input plane into its (TX+1) x (TY+1) LDS tile.  The tile
   // holds global points (x0 - ox + lx, y0 - oy + ly), with ox (oy) = 1 for an
-  // input cell-centred along x (y).  Thread t loads the interior point of its
-  // own output position (a wave reads whole aligned row segments) and, for
+  // input cell-centred along x (y).  Staging thread t loads SE interior
+  // points, x-adjacent on pair and wide tiles (a wave reads whole aligned
+  // row segments; they need not be the points t updates) and, for
   // t < TY + TX, one halo point: of the halo column read by x differences
   // (lx = 0 or TX) or of the halo row read by y differences (ly = 0 or TY);
   // the corners are never read.  Source and LDS offsets are affine in (ox, oy):
