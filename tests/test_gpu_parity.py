@@ -252,6 +252,43 @@ def test_bf16_tile_variants_are_bitwise_identical(bc, monkeypatch):
     assert_parity(ref, o.u, 2e-2, f"BF16 {bc} vs oracle:", moment_tol=1e-1, elem_tol=5e-2)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("bc", [("periodic", "periodic"), ("extrapolation", "periodic")])
+def test_grid_of_whole_tiles_variants_are_bitwise_identical(precision, bc, monkeypatch):
+    """A 128 x 64 grid holds whole tiles of every variant, so every tile takes
+    the pair and wide paths (no right-edge tile with single accesses) and the
+    halo of the last tile column wraps or clamps at the grid's edge.  Every
+    variant gives the same bits, and the result matches the oracle."""
+    prob = wl.random_medium(36, 9, 128, t_final=0.2, precision=precision)
+    prob.n = (128, 64)
+    prob.bc = bc
+    ref, tried = None, []
+    for width in (4, 6):
+        monkeypatch.setenv("STARMAP_CHUNK_WIDTH", str(width))
+        for v in range(pa.variant_count()):
+            s = pa.Solver.from_problem(prob, precision=precision)
+            s.bind_torch()
+            try:
+                s.set_variant(v)
+            except pa.StarmapError:
+                continue
+            tried.append((v, width))
+            s.advance(6)
+            out = s.moments()
+            s.close()
+            if ref is None:
+                ref = out
+            else:
+                for a, b in zip(out, ref):
+                    assert np.array_equal(a, b), f"variant {v} width {width} differs"
+    assert len(tried) >= 8
+    o = run_oracle(prob, nsteps=6)
+    if precision == "fp32":
+        assert_parity(ref, o.u, FP32_TOL, f"FP32 {bc} 128x64 vs oracle:")
+    else:
+        assert_parity(ref, o.u, 2e-2, f"BF16 {bc} 128x64 vs oracle:", moment_tol=1e-1, elem_tol=5e-2)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
 def test_c2_checkerboard_full_run(precision, tol):
     prob = wl.config("c2")
